@@ -1,0 +1,225 @@
+"""ctypes shim for the CPU FP64 oracle (``oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark, never by the library.  It imports nothing
+from the library package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "oracle.cpp")
+
+_d = C.POINTER(C.c_double)
+_i = C.POINTER(C.c_int32)
+
+
+def build(force=True):
+    """Compile the oracle with g++ (OpenMP over cells)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", SRC, "-o", tmp])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = C.CDLL(LIB)
+        L.or_mech_load.restype = C.c_void_p
+        L.or_mech_load.argtypes = [C.c_char_p]
+        L.or_mech_free.argtypes = [C.c_void_p]
+        L.or_mech_dims.argtypes = [C.c_void_p, _i, _i, _i]
+        L.or_mech_arrays.argtypes = [C.c_void_p, _d, _i, _d]
+        L.or_thermo.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
+        L.or_kinetics.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d, _d, _d, _d, _d]
+        L.or_rhs.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
+        L.or_jacobian.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
+        L.or_lu_solve.argtypes = [C.c_int, _d, _d, _d]
+        L.or_ros4_table.argtypes = [_d]
+        L.or_step.argtypes = [C.c_void_p, C.c_double, _d, C.c_double, _d, _d]
+        L.or_to_phi.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d]
+        L.or_from_phi.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
+        L.or_integrate.restype = C.c_int
+        L.or_integrate.argtypes = [C.c_void_p, C.c_int64, _d, _d, _d, C.c_int64, C.c_double, C.c_double,
+                                   C.c_double, _d, _d, _d, _i, _i, _i, _d, C.c_int, C.c_int]
+        L.or_record_steps.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, _d, _d, C.c_int, _d, _d]
+        L.or_replay.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d, _d, C.c_int, _d, _d]
+        L.or_tangent.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d, _d, C.c_int, _d,
+                                 C.c_double, _d, _d, _d]
+        L.or_integrate_linear.argtypes = [C.c_int, _d, _d, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.or_integrate_riccati.argtypes = [_d, C.c_double, C.c_double, C.c_double, C.c_double]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.flags.c_contiguous
+    if a.dtype == np.float64:
+        return a.ctypes.data_as(_d)
+    if a.dtype == np.int32:
+        return a.ctypes.data_as(_i)
+    raise TypeError(a.dtype)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+R_U = 8314.462618
+P_ATM = 101325.0
+
+
+class Oracle:
+    """One parsed mechanism in the oracle."""
+
+    def __init__(self, path):
+        self.L = lib()
+        self.h = self.L.or_mech_load(path.encode())
+        if not self.h:
+            raise ValueError("oracle could not parse %s" % path)
+        K, Nr, E = C.c_int32(), C.c_int32(), C.c_int32()
+        self.L.or_mech_dims(self.h, C.byref(K), C.byref(Nr), C.byref(E))
+        self.K, self.Nr, self.E = K.value, Nr.value, E.value
+        self.N = self.K + 1
+        self.W = np.zeros(self.K)
+        self.comp = np.zeros((self.K, self.E), np.int32)
+        self.lnA = np.zeros(self.Nr)
+        self.L.or_mech_arrays(self.h, _p(self.W), _p(self.comp), _p(self.lnA))
+
+    def __del__(self):
+        try:
+            self.L.or_mech_free(self.h)
+        except Exception:
+            pass
+
+    # -- pieces ---------------------------------------------------------------
+    def thermo(self, T):
+        cp, h, s = (np.zeros(self.K) for _ in range(3))
+        self.L.or_thermo(self.h, float(T), _p(cp), _p(h), _p(s))
+        return cp, h, s
+
+    def kinetics(self, T, P, Cc, lnA=None):
+        Cc = _f64(Cc)
+        q, kf, kr = (np.zeros(self.Nr) for _ in range(3))
+        w = np.zeros(self.K)
+        self.L.or_kinetics(self.h, float(T), float(P), _p(Cc), _p(_f64(lnA)), _p(q), _p(w), _p(kf), _p(kr))
+        return q, w, kf, kr
+
+    def rhs(self, P, phi, lnA=None):
+        f = np.zeros(self.N)
+        self.L.or_rhs(self.h, float(P), _p(_f64(phi)), _p(_f64(lnA)), _p(f))
+        return f
+
+    def jacobian(self, P, phi, lnA=None):
+        J = np.zeros((self.N, self.N))
+        self.L.or_jacobian(self.h, float(P), _p(_f64(phi)), _p(_f64(lnA)), _p(J))
+        return J
+
+    def step(self, P, phi, h):
+        out, err = np.zeros(self.N), np.zeros(self.N)
+        rc = self.L.or_step(self.h, float(P), _p(_f64(phi)), float(h), _p(out), _p(err))
+        return rc, out, err
+
+    def to_phi(self, T, P, Y):
+        phi = np.zeros(self.N)
+        self.L.or_to_phi(self.h, float(T), float(P), _p(_f64(Y)), _p(phi))
+        return phi
+
+    def from_phi(self, P, phi):
+        T = np.zeros(1)
+        Y = np.zeros(self.K)
+        self.L.or_from_phi(self.h, float(P), _p(_f64(phi)), _p(T), _p(Y))
+        return T[0], Y
+
+    # -- batched integration ---------------------------------------------------
+    def integrate(self, T, P, Y, dt, rtol=1e-6, atol=1e-10, h=None, lnA=None, max_steps=0,
+                  nthreads=0):
+        """Y is (K, n).  Returns dict with T, Y, h, n_acc, n_rej, status, threads."""
+        T = _f64(T)
+        P = _f64(P)
+        Y = _f64(Y)
+        n = T.size
+        assert Y.shape == (self.K, n)
+        Tout = np.zeros(n)
+        Yout = np.zeros_like(Y)
+        hio = np.zeros(n) if h is None else _f64(h).copy()
+        na, nr, st = (np.zeros(n, np.int32) for _ in range(3))
+        thr = self.L.or_integrate(self.h, n, _p(T), _p(P), _p(Y), n, float(dt), float(rtol), float(atol),
+                                  _p(hio), _p(Tout), _p(Yout), _p(na), _p(nr), _p(st), _p(_f64(lnA)),
+                                  int(max_steps), int(nthreads))
+        return dict(T=Tout, Y=Yout, h=hio, n_acc=na, n_rej=nr, status=st, threads=thr)
+
+    def record_steps(self, T, P, Y, dt, rtol=1e-6, atol=1e-10, h0=0.0, lnA=None, cap=1000000):
+        hs = np.zeros(cap)
+        To = np.zeros(1)
+        Yo = np.zeros(self.K)
+        n = self.L.or_record_steps(self.h, float(T), float(P), _p(_f64(Y)), float(dt), float(rtol),
+                                   float(atol), float(h0), _p(_f64(lnA)), _p(hs), cap, _p(To), _p(Yo))
+        if n < 0:
+            raise RuntimeError("oracle integration failed with status %d" % -n)
+        return hs[:n].copy(), To[0], Yo
+
+    def replay(self, T, P, Y, hs, lnA=None):
+        To = np.zeros(1)
+        Yo = np.zeros(self.K)
+        hs = _f64(hs)
+        rc = self.L.or_replay(self.h, float(T), float(P), _p(_f64(Y)), _p(_f64(lnA)), _p(hs), hs.size,
+                              _p(To), _p(Yo))
+        if rc:
+            raise RuntimeError("replay failed")
+        return To[0], Yo
+
+    def tangent(self, T, P, Y, hs, v_lnA=None, dT0=0.0, dY0=None, lnA=None):
+        dT = np.zeros(1)
+        dY = np.zeros(self.K)
+        hs = _f64(hs)
+        self.L.or_tangent(self.h, float(T), float(P), _p(_f64(Y)), _p(_f64(lnA)), _p(hs), hs.size,
+                          _p(_f64(v_lnA)), float(dT0), _p(_f64(dY0)), _p(dT), _p(dY))
+        return dT[0], dY
+
+
+def ros4_table():
+    t = np.zeros(18)
+    lib().or_ros4_table(_p(t))
+    names = "gamma a21 a31 a32 c21 c31 c32 c41 c42 c43 m1 m2 m3 m4 e1 e2 e3 e4".split()
+    return dict(zip(names, t))
+
+
+def lu_solve(A, b):
+    A = _f64(A)
+    b = _f64(b)
+    x = np.zeros_like(b)
+    rc = lib().or_lu_solve(b.size, _p(A), _p(b), _p(x))
+    if rc:
+        raise np.linalg.LinAlgError("singular")
+    return x
+
+
+def integrate_linear(A, y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0):
+    A = _f64(A)
+    y = _f64(y0).copy()
+    n = lib().or_integrate_linear(y.size, _p(A), _p(y), float(dt), float(rtol), float(atol), float(h_fixed))
+    return y, n
+
+
+def integrate_riccati(y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0):
+    y = np.array([float(y0)])
+    n = lib().or_integrate_riccati(_p(y), float(dt), float(rtol), float(atol), float(h_fixed))
+    return y[0], n
