@@ -1,0 +1,144 @@
+/*
+ * chem.h - C ABI of the batched FP64 ROS4 chemistry integrator for MI355X (gfx950).
+ *
+ * Every cell of a CFD domain (or sub-domain) is advanced independently over one
+ * operator-splitting step at constant pressure.  The state of a cell is
+ * Phi = {T, V, n_1 .. n_{K-1}} per unit mass, the last species being the bath
+ * gas closed by the ideal-gas law (paper Sec. 2.1, eqs. (state_vec), (n_nsp)).
+ * Each cell is integrated with the four-stage, fourth-order linearly implicit
+ * Rosenbrock method ROS4 in the transformed form of Sec. 2.3 (one LU of
+ * (I/(h gamma) - J) per step, analytical Jacobian J of eq. (jac)), with
+ * adaptive steps from rtol/atol (Sec. 3.1).  One batched call integrates all
+ * cells, and each cell's last internal step is returned for reuse as its next
+ * initial step (Sec. 2.4.1, the batched chemistry model).
+ *
+ * Conventions
+ *  - Units: SI.  T in K, P in Pa, dt and h in s, W in kg/kmol.
+ *  - Layout: species arrays are structure-of-arrays, Y[k * ldY + cell], the
+ *    cell index fastest; ldY >= n_cells.
+ *  - Pointers to states, outputs and parameters are DEVICE pointers owned by
+ *    the caller; the library never frees them.  Handles, workspaces and
+ *    checkpoints are library-owned and released by the matching *_free call.
+ *  - All calls are asynchronous on `stream` (0 = the null stream); none
+ *    synchronises the host unless stated.
+ *  - Return codes: 0 success; negative on API errors (see CHEM_E*).  A cell
+ *    that fails to integrate does not fail the call: its outcome goes to
+ *    status[cell] (CHEM_CELL_*) and it keeps its last accepted state.
+ *  - A handle is immutable after load and may be used from several streams;
+ *    calls on one stream are ordered, calls on different streams use
+ *    separate workspaces.
+ */
+#ifndef CHEM_H
+#define CHEM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define CHEM_OK 0
+#define CHEM_EINVAL (-1)       /* null pointer, n < 0, dt <= 0, rtol <= 0, ldY < n, bad option */
+#define CHEM_EPARSE (-2)       /* mechanism file missing or malformed */
+#define CHEM_EHIP (-3)         /* HIP runtime error */
+#define CHEM_ENOMEM (-4)       /* device allocation failed */
+#define CHEM_EUNSUPPORTED (-5) /* mechanism larger than the compiled limits */
+
+/* ---- per-cell outcome (status[cell]) ----------------------------------- */
+#define CHEM_CELL_OK 0
+#define CHEM_CELL_MAX_STEPS 1  /* max_steps attempts reached before dt */
+#define CHEM_CELL_H_MIN 2      /* step size fell below h_min */
+#define CHEM_CELL_NONFINITE 3  /* ten consecutive non-finite steps */
+#define CHEM_CELL_SINGULAR 4   /* ten consecutive zero pivots */
+
+/* ---- scheduling modes (chem_opts.mode) ---------------------------------- */
+#define CHEM_MODE_AUTO 0        /* autotuned choice (cached per mechanism/size) */
+#define CHEM_MODE_PLAIN 1       /* one cell per thread, one launch of ceil(n/wg) groups */
+#define CHEM_MODE_PERSISTENT 2  /* one cell per thread, resident grid, atomic work queue */
+#define CHEM_MODE_TEAM 3        /* one wavefront per cell (J and LU in registers/LDS) */
+#define CHEM_MODE_TEAM_PERSISTENT 4 /* one wavefront per cell, resident grid, work queue */
+
+typedef struct chem_mech_s* chem_mech_t; /* opaque, library-owned */
+typedef struct chem_ckpt_s* chem_ckpt_t; /* opaque, library-owned adjoint checkpoint */
+
+/* Integration options.  Fill with chem_opts_default() and override. */
+typedef struct {
+  double rtol, atol;      /* ignored here: the chem_integrate arguments rule */
+  double h_min;           /* smallest step before CHEM_CELL_H_MIN (1e-20 s) */
+  double safety;          /* step-size safety factor (0.9) */
+  double fac_min;         /* smallest step ratio (0.2) */
+  double fac_max;         /* largest step ratio (6) */
+  double T_cut;           /* cells with T_in < T_cut are copied, not integrated (0 = off) */
+  int32_t max_steps;      /* attempted steps per cell before CHEM_CELL_MAX_STEPS (100000) */
+  int32_t mode;           /* CHEM_MODE_* */
+  int32_t wg_size;        /* work-group size in threads (0 = library choice) */
+  int32_t waves_per_cu;   /* persistent modes: resident waves per CU (0 = occupancy limit) */
+} chem_opts;
+
+/* Defaults listed above. */
+void chem_opts_default(chem_opts* o);
+
+/* Parse the text mechanism at `path` (format in the library's generator
+ * documentation: species with NASA-7 coefficients, reversible reactions of
+ * elementary, third-body, Lindemann and Troe type) and upload its tables to
+ * `device`.  *out receives the handle.  Errors: CHEM_EPARSE, CHEM_EUNSUPPORTED
+ * (more than 255 species or 4095 reactions), CHEM_EHIP, CHEM_ENOMEM. */
+int chem_mech_load(const char* path, int device, chem_mech_t* out);
+
+/* Species, reaction and element counts of a loaded mechanism. */
+int chem_mech_info(chem_mech_t m, int32_t* n_species, int32_t* n_reactions, int32_t* n_elements);
+
+/* Release the handle, its device tables and every cached workspace
+ * (synchronises the device). */
+void chem_mech_free(chem_mech_t m);
+
+/* Integrate n_cells cells over [0, dt] (one split step).
+ *   T_in[n], P[n], Y_in[K][ldY]  initial temperature, pressure, mass fractions
+ *   T_out[n], Y_out[K][ldY]      results; may alias T_in / Y_in
+ *   h_io[n]   nullable; in: first step per cell (<= 0 means dt), out: the
+ *             controller's next step after the last accepted one
+ *   n_steps[n], status[n]  nullable int32 outputs: accepted steps, outcome
+ *   lnA[Nr]   nullable; replaces every reaction's ln A (falloff reactions
+ *             move their low-pressure A by the same factor), for
+ *             differentiation with respect to ln A
+ *   opts      nullable (defaults)
+ *   ckpt_out  nullable; non-null records every accepted step (state, h and
+ *             the four stage vectors) for chem_integrate_adjoint; *ckpt_out
+ *             receives a new checkpoint that the caller frees
+ * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM.  Asynchronous on `stream`. */
+int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const double* P,
+                   const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
+                   double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
+                   const double* lnA, const chem_opts* opts, chem_ckpt_t* ckpt_out,
+                   hipStream_t stream);
+
+/* Discrete adjoint of the checkpointed integration: reverse sweep over every
+ * cell's accepted steps with the step sizes frozen.
+ *   gT[n], gY[K][ldY]   dL/dT_final, dL/dY_final (device)
+ *   g_lnA               [Nr] dL/d ln A summed over cells (per_cell = 0) or
+ *                       [Nr][n] per cell (per_cell = 1), overwritten
+ *   gT0[n], gY0[K][ldY] nullable: dL/dT_in, dL/dY_in
+ * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM. */
+int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, const double* gY,
+                           int64_t ldY, double* g_lnA, int32_t per_cell, double* gT0,
+                           double* gY0, hipStream_t stream);
+
+/* Release a checkpoint (synchronises its stream). */
+void chem_ckpt_free(chem_ckpt_t c);
+
+/* Evaluate the source terms f(Phi) (eq. (dphidt)) and, if J is non-null, the
+ * dense Jacobian (eq. (jac)) for n cells.  phi[N][ld], f[N][ld],
+ * J[N*N][ld] (row-major element (i, j) at J[(i*N + j)*ld + cell]), P[n].
+ * lnA nullable as in chem_integrate.  For testing the pieces of a step. */
+int chem_eval(chem_mech_t m, int64_t n, const double* phi, int64_t ld, const double* P,
+              const double* lnA, double* f, double* J, hipStream_t stream);
+
+/* Human-readable text of a return code. */
+const char* chem_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEM_H */

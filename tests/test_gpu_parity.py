@@ -1,0 +1,228 @@
+"""Parity of the HIP integrator with the CPU FP64 oracle (through the C ABI).
+
+Bar, per cell: |T_gpu - T_or| <= 1e-6 T_or and |Y_gpu - Y_or| <= 1e-6 |Y_or|
++ 1e-10 (rtol 1e-6 on T and Y, atol 1e-10).  Both sides run the same
+algorithm and controller; they differ only in rounding (FMA contraction,
+summation order, device vs host exp/log).  Cells that take hundreds of steps
+through a thermal runaway amplify rounding differences: the oracle itself
+moves some of them past the bar when its input changes by one part in 1e15.
+Such a cell passes when it lies within twice the oracle's own envelope under
+that perturbation, and such cells must be rare.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2205_05681_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def chem():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_05681_amd import chem as C
+    C.lib()
+    return C
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def off_cells(Tg, Yg, To, Yo):
+    okT = np.abs(Tg - To) <= 1e-6 * np.abs(To)
+    okY = np.abs(Yg - Yo) <= 1e-6 * np.abs(Yo) + 1e-10
+    return np.where(~okT | ~okY.all(0))[0]
+
+
+def assert_parity(Tg, Yg, To, Yo, label, o=None, inputs=None, dt=None, max_frac=0.08, h=None):
+    """Every cell within the bar - or, for a cell whose result the oracle itself
+    moves past the bar under a 1e-15 / 1e-13 relative change of its input
+    temperature (a rounding-chaotic cell: hundreds of steps through a thermal
+    runaway), within twice that envelope of the oracle.  Such cells must stay
+    rare (max_frac)."""
+    bad = off_cells(Tg, Yg, To, Yo)
+    if bad.size == 0:
+        return
+    assert o is not None, "%s: %d cells off, first %s: dT %g, max dY %g" % (
+        label, bad.size, bad[:5], np.abs(Tg - To)[bad[0]], np.abs(Yg - Yo)[:, bad[0]].max())
+    assert bad.size <= max_frac * Tg.size, "%s: %d of %d cells off" % (label, bad.size, Tg.size)
+    T, P, Y = inputs
+    envT = np.zeros(bad.size)
+    envY = np.zeros((Y.shape[0], bad.size))
+    for eps in (1e-15, -1e-15, 1e-13, -1e-13):
+        r = o.integrate(T[bad] * (1 + eps), P[bad], Y[:, bad].copy(), dt,
+                        h=None if h is None else h[bad])
+        envT = np.maximum(envT, np.abs(r["T"] - To[bad]))
+        envY = np.maximum(envY, np.abs(r["Y"] - Yo[:, bad]))
+    dT = np.abs(Tg[bad] - To[bad])
+    dY = np.abs(Yg[:, bad] - Yo[:, bad])
+    barT = 1e-6 * np.abs(To[bad])
+    barY = 1e-6 * np.abs(Yo[:, bad]) + 1e-10
+    chaotic = (envT > barT) | (envY > barY).any(0)
+    assert chaotic.all(), "%s: cells %s off but not rounding-sensitive" % (label, bad[~chaotic])
+    assert np.all(dT <= barT + 2 * envT), label
+    assert np.all(dY <= barY + 2 * envY), label
+
+
+def run_gpu(C, mech, T, P, Y, dt, mode="plain", h=None, **kw):
+    opts = C.default_opts(mode=mode, **kw)
+    hh = None if h is None else dev(h)
+    T1, Y1, h1, ns, st = C.integrate(mech, dev(T), dev(P), dev(Y), dt, h=hh, opts=opts)
+    torch.cuda.synchronize()
+    return T1.cpu().numpy(), Y1.cpu().numpy(), h1.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["small", "ch4", "large"])
+def test_rhs_and_jacobian_parity(chem, name, request):
+    path, m, o = request.getfixturevalue(name)
+    say("case: rhs/jacobian parity", name)
+    mech = chem.Mechanism(path)
+    rng = np.random.default_rng(17)
+    n = 70
+    phis, Ps = [], []
+    for _ in range(n):
+        T = rng.uniform(320, 2600)
+        if abs(T - 1000) < 1:
+            T += 3
+        Y = rng.dirichlet(np.ones(o.K))
+        P = rng.uniform(1, 5) * 101325.0
+        phis.append(o.to_phi(T, P, Y))
+        Ps.append(P)
+    phi = np.array(phis).T.copy()
+    P = np.array(Ps)
+    f, J = chem.evaluate(mech, dev(phi), dev(P))
+    torch.cuda.synchronize()
+    f = f.cpu().numpy()
+    J = J.cpu().numpy().reshape(o.N, o.N, n)
+    for c in range(n):
+        fo = o.rhs(P[c], phi[:, c])
+        Jo = o.jacobian(P[c], phi[:, c])
+        assert np.allclose(f[:, c], fo, rtol=1e-10, atol=1e-12 * np.abs(fo).max()), c
+        # entrywise to 1e-9 of the row scale (J rows mix magnitudes)
+        scale = np.abs(Jo).max(1, keepdims=True) + 1e-300
+        assert np.abs(J[:, :, c] - Jo).max() <= 1e-9 * scale.max(), c
+        assert np.all(np.abs(J[:, :, c] - Jo) <= 1e-9 * scale), c
+    mech.close()
+
+
+def test_small_parity_full_config(chem, small):
+    path, m, o = small
+    say("case: small mechanism, 256 cells, plain")
+    T, P, Y = synth.states_small(m)
+    mech = chem.Mechanism(path)
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6)
+    r = o.integrate(T, P, Y, 1e-6)
+    assert np.all(sg == 0) and np.all(r["status"] == 0)
+    assert_parity(Tg, Yg, r["T"], r["Y"], "small", o, (T, P, Y), 1e-6)
+    # hundreds of steps per cell: a few accept/reject decisions differ by rounding
+    assert np.mean(ng == r["n_acc"]) >= 0.8
+    # the returned step is the controller's proposal, err^(-1/4) of an O(rtol)
+    # difference quantity: on these rounding-chaotic cells it agrees only loosely
+    rel = np.abs(hg - r["h"]) / r["h"]
+    assert np.median(rel) < 1e-3 and np.mean(rel < 0.5) > 0.95
+    mech.close()
+
+
+@pytest.mark.parametrize("mode", ["plain", "persistent"])
+def test_ch4_parity_ragged(chem, ch4, mode):
+    """1,000 mixing-layer cells (15 full wavefronts and a ragged tail)."""
+    path, m, o = ch4
+    say("case: ch4 mechanism, 1000 cells,", mode)
+    T, P, Y = synth.states_mixing(m, 1000, 202)
+    mech = chem.Mechanism(path)
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
+    r = o.integrate(T, P, Y, 1e-6)
+    assert np.all(sg == 0)
+    assert_parity(Tg, Yg, r["T"], r["Y"], "ch4 " + mode, o, (T, P, Y), 1e-6, max_frac=0.01)
+    assert np.mean(ng == r["n_acc"]) >= 0.99
+    rel = np.abs(hg - r["h"]) / r["h"]
+    assert np.mean(rel < 1e-6) >= 0.97
+    mech.close()
+
+
+def test_ch4_full_size_sampled(chem, ch4):
+    """65,536 cells in the benchmark's launch; 96 cells re-run on the oracle,
+    the hottest ones included."""
+    path, m, o = ch4
+    say("case: ch4 mechanism, 65536 cells sampled, plain + persistent")
+    T, P, Y = synth.states_mixing(m, 65536, 202)
+    mech = chem.Mechanism(path)
+    res = {}
+    for mode in ("plain", "persistent"):
+        res[mode] = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
+    # the two launches run the same per-cell arithmetic
+    assert np.array_equal(res["plain"][0], res["persistent"][0])
+    assert np.array_equal(res["plain"][1], res["persistent"][1])
+    Tg, Yg, hg, ng, sg = res["plain"]
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.r_[rng.choice(65536, 64, replace=False), np.argsort(-ng)[:32]])
+    r = o.integrate(T[idx], P[idx], Y[:, idx].copy(), 1e-6)
+    assert_parity(Tg[idx], Yg[:, idx], r["T"], r["Y"], "ch4 full", o, (T[idx], P[idx], Y[:, idx]),
+                  1e-6, max_frac=0.03)
+    assert np.mean(ng[idx] == r["n_acc"]) >= 0.97
+    mech.close()
+
+
+def test_large_parity_small_batch(chem, large):
+    path, m, o = large
+    say("case: large mechanism, 130 cells, plain")
+    T, P, Y = synth.states_mixing(m, 130, 204)
+    mech = chem.Mechanism(path)
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-5)
+    r = o.integrate(T, P, Y, 1e-5)
+    assert np.all(sg == 0)
+    assert_parity(Tg, Yg, r["T"], r["Y"], "large", o, (T, P, Y), 1e-5, max_frac=0.03)
+    mech.close()
+
+
+def test_step_carry_over_and_edge_cases(chem, small):
+    path, m, o = small
+    say("case: edge cases (h carry-over, n=1, max_steps, NaN, T_cut, bad args)")
+    mech = chem.Mechanism(path)
+    T, P, Y = synth.states_small(m, n=65, seed=7)
+    # two consecutive split steps, h carried over like the CFD coupling does
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6)
+    Tg2, Yg2, hg2, ng2, sg2 = run_gpu(chem, mech, Tg, P, Yg, 1e-6, h=hg)
+    # the second step starts from slightly different states; compare it from the
+    # GPU's own first-step output so that only the second step is tested
+    r2g = o.integrate(Tg, P, Yg, 1e-6, h=hg)
+    assert_parity(Tg2, Yg2, r2g["T"], r2g["Y"], "carry-over", o, (Tg, P, Yg), 1e-6, max_frac=0.2,
+                  h=hg)
+    # a single cell
+    Tg1, Yg1, *_ = run_gpu(chem, mech, T[:1], P[:1], Y[:, :1].copy(), 1e-6)
+    assert np.array_equal(Tg1, Tg[:1]) and np.array_equal(Yg1, Yg[:, :1])
+    # forced failures: max_steps, non-finite state
+    *_, st = run_gpu(chem, mech, T, P, Y, 1e-6, max_steps=1)
+    assert np.all(st == chem.CELL_MAX_STEPS)
+    Tn = T.copy()
+    Tn[3] = np.nan
+    Tgn, _, _, _, st = run_gpu(chem, mech, Tn, P, Y, 1e-6)
+    assert st[3] == chem.CELL_NONFINITE and np.all(np.delete(st, 3) == 0)
+    assert np.allclose(np.delete(Tgn, 3), np.delete(Tg, 3), rtol=0, atol=0)
+    # cells below T_cut are passed through
+    Tc, Yc, _, nc, _ = run_gpu(chem, mech, T, P, Y, 1e-6, T_cut=1500.0)
+    cold = T < 1500.0
+    assert np.all(nc[cold] == 0) and np.allclose(Tc[cold], T[cold], rtol=1e-15)
+    assert np.allclose(Yc[:, cold], Y[:, cold], rtol=1e-12, atol=1e-16)
+    assert np.array_equal(Tc[~cold], Tg[~cold]) and np.array_equal(Yc[:, ~cold], Yg[:, ~cold])
+    # empty batch and argument errors
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    chem.integrate(mech, e, e, torch.empty((mech.K, 0), dtype=torch.float64, device="cuda"), 1e-6)
+    with pytest.raises(chem.ChemError) as ei:
+        chem.integrate(mech, dev(T), dev(P), dev(Y), -1.0)
+    assert ei.value.code == chem.EINVAL
+    with pytest.raises(chem.ChemError):
+        chem.integrate(mech, dev(T), dev(P), dev(Y), 1e-6, rtol=0.0)
+    mech.close()
