@@ -1,0 +1,217 @@
+"""Benchmark: cells integrated per second over one operator-splitting step.
+
+Workload (default): the CH4-shaped synthetic mechanism (53 species, 325
+reversible reactions, 30 third-body, 25 Troe) over 65,536 mixing-layer cells
+(P ~ U[1, 5] atm, Z ~ Beta(2, 5), T = linear mix of 300 K fuel and 800 K air
+plus N(0, 200^2) K), dt = 1e-6 s, FP64, rtol 1e-6, atol 1e-10.  One step = one
+chem_integrate call over every cell with the inputs resident in HBM.
+
+Prints one JSON line (rank 0).  Extra keys: "roofline" for the integrator
+kernel (algorithmic FP64 flops per launch over its average launch duration,
+measured with HIP events on the launch stream), "cpu_baseline" (the CPU
+oracle on a bounded sample of the same cells, on this host's cores) and
+"modes" (cells/s of each launch mode of the library on this workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import tempfile
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+KERNEL_SOURCES = ["paper_2205_05681_amd/csrc/integrate.hip", "paper_2205_05681_amd/csrc/team.h",
+                  "paper_2205_05681_amd/csrc/kinetics.h", "paper_2205_05681_amd/csrc/ros4.h",
+                  "paper_2205_05681_amd/csrc/mech.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_team_kernel_ch4_65536.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name, synth, mech_dir):
+    if name == "ch4_mixing":
+        path, m = synth.mechanism_file("ch4", mech_dir)
+        T, P, Y = synth.states_mixing(m, 65536, 202)
+        desc = ("CH4-shaped synthetic mechanism (53 species, 325 reactions: 30 third-body, 25 Troe), "
+                "65,536 mixing-layer cells, P~U[1,5] atm, Z~Beta(2,5), dt=1e-6 s, rtol 1e-6, atol 1e-10")
+        return path, m, T, P, Y, 1e-6, desc
+    if name == "ch4_batching":
+        path, m = synth.mechanism_file("ch4", mech_dir)
+        T, P, Y, _ = synth.states_batching(m, 1048576, 203)
+        desc = ("CH4-shaped synthetic mechanism, 1,048,576 cells: 85% cold (<800 K), 10% stoichiometric "
+                "1100-1400 K, 5% burnt gas; dt=1e-5 s, rtol 1e-6, atol 1e-10")
+        return path, m, T, P, Y, 1e-5, desc
+    if name == "small":
+        path, m = synth.mechanism_file("small", mech_dir)
+        T, P, Y = synth.states_small(m, 256, 201)
+        desc = "H2/O2-shaped synthetic mechanism (10 species, 25 reactions), 256 cells, dt=1e-6 s"
+        return path, m, T, P, Y, 1e-6, desc
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(oracle, path, T, P, Y, dt, budget_s):
+    """The oracle (as it is) on the first cells of the workload, in chunks of
+    512, until about budget_s seconds of CPU work."""
+    import numpy as np
+    o = oracle.Oracle(path)
+    done, t0, threads = 0, time.time(), 0
+    n = T.size
+    while done < n and (time.time() - t0) < budget_s:
+        c = slice(done, min(done + 512, n))
+        r = o.integrate(T[c], P[c], np.ascontiguousarray(Y[:, c]), dt)
+        threads = r["threads"]
+        done = c.stop
+    el = time.time() - t0
+    return {"value": done / el, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
+            "sample": "first %d of the %d cells, %.1f s wall on %d threads" % (done, n, el, threads)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ch4_mixing")
+    ap.add_argument("--mode", default="auto", help="headline launch mode")
+    ap.add_argument("--compare", default="team,plain,persistent",
+                    help="other modes to time (thread-per-cell modes take one step)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 256 MiB device copy (reference for HBM byte counters)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported "
+              "(cells are independent, see the sharding notes)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2205_05681_amd import chem, opcount, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    mech_dir = tempfile.mkdtemp(prefix="chem_bench_")
+    path, m, T, P, Y, dt, desc = workload(a.workload, synth, mech_dir)
+    n = T.size
+    mech = chem.Mechanism(path, device=0)
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    Tt, Pt, Yt = d(T), d(P), d(Y)
+    T1 = torch.empty_like(Tt)
+    Y1 = torch.empty_like(Yt)
+    h = torch.zeros(n, dtype=torch.float64, device=dev)
+    ns = torch.empty(n, dtype=torch.int32, device=dev)
+    st = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def step(mode):
+        h.zero_()
+        chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=chem.default_opts(mode=mode), out=(T1, Y1),
+                       n_steps=ns, status=st)
+
+    if a.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # ---- headline mode: W warmup steps, then K timed steps
+    for _ in range(a.warmup):
+        step(a.mode)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    opts = chem.default_opts(mode=a.mode)
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        h.zero_()
+        ev[i][0].record(stream)
+        chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=opts, out=(T1, Y1), n_steps=ns, status=st)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [s.elapsed_time(e) for s, e in ev]
+    ms_per_step = wall * 1e3 / a.steps
+    value = n / (wall / a.steps)
+    status = st.cpu().numpy()
+    steps_acc = ns.cpu().numpy()
+
+    # ---- step statistics of the same call (deterministic), for the op count
+    stats = torch.zeros(3, dtype=torch.int64, device=dev)
+    h.zero_()
+    chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=chem.default_opts(mode=a.mode, stats=stats), out=(T1, Y1))
+    torch.cuda.synchronize()
+    attempts, accepted, rejected = (int(x) for x in stats.cpu().numpy())
+    flops, trans = opcount.batch_flops(m, attempts, accepted)
+    avg_launch_s = float(np.mean(launch_ms)) / 1e3
+    achieved = flops / avg_launch_s / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("kernel_hash") == kernel_hash() and tf.get("workload") == a.workload:
+            traffic = tf.get("hbm_bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 6), "traffic": traffic,
+                "kernel": "integrate_team_kernel" if a.mode in ("auto", "team", "team_persistent") else
+                "integrate_thread_kernel",
+                "flops_per_launch": flops, "transcendentals_per_launch": trans,
+                "attempted_steps": attempts, "accepted_steps": accepted,
+                "avg_launch_ms": round(avg_launch_s * 1e3, 4)}
+
+    # ---- other launch modes on the same cells
+    modes = {a.mode: round(value, 1)}
+    for mode in [x for x in a.compare.split(",") if x and x != a.mode]:
+        reps = 1 if mode in ("plain", "persistent") else max(1, a.steps // 2)
+        step(mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            step(mode)
+        torch.cuda.synchronize()
+        modes[mode] = round(n / ((time.perf_counter() - t) / reps), 1)
+
+    cpu = None
+    if not a.no_cpu:
+        import oracle
+        cpu = cpu_baseline(oracle, path, T, P, Y, dt, a.cpu_seconds)
+
+    out = {
+        "metric": "cells/s per split step at rtol 1e-6",
+        "value": round(value, 1),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "cells": n, "species": m.n_species, "reactions": len(m.reactions),
+                   "dt": dt, "rtol": 1e-6, "atol": 1e-10, "mode": a.mode,
+                   "failed_cells": int((status != 0).sum()),
+                   "accepted_steps_mean": round(float(steps_acc.mean()), 3),
+                   "accepted_steps_max": int(steps_acc.max())},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "modes": modes,
+    }
+    print(json.dumps(out), flush=True)
+    mech.close()
+
+
+if __name__ == "__main__":
+    main()

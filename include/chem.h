@@ -75,6 +75,8 @@ typedef struct {
   int32_t mode;           /* CHEM_MODE_* */
   int32_t wg_size;        /* work-group size in threads (0 = library choice) */
   int32_t waves_per_cu;   /* persistent modes: resident waves per CU (0 = occupancy limit) */
+  unsigned long long* stats; /* nullable DEVICE pointer to 3 counters that the call adds to:
+                                attempted steps, accepted steps, rejected steps (all cells) */
 } chem_opts;
 
 /* Defaults listed above. */

@@ -26,6 +26,7 @@
 #include "kinetics.h"
 #include "mech.h"
 #include "ros4.h"
+#include "team.h"
 
 namespace chem {
 
@@ -48,6 +49,7 @@ struct IntParams {
   int32_t* piv;
   int64_t ld;
   unsigned int* queue;
+  unsigned long long* stats;   // nullable: attempts, accepted, rejected
   // adjoint checkpoint (nullable): per cell, accepted (Phi_n, h) records
   double* ck_data;          // [rec][N+1] per record, cell-major blocks
   const int64_t* ck_off;    // [n+1] record offsets per cell
@@ -198,6 +200,11 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
     if (p.n_steps) p.n_steps[c] = accepted;
     if (p.status) p.status[c] = status;
     if (p.ck_count) p.ck_count[c] = accepted;
+    if (p.stats) {
+      atomicAdd(&p.stats[0], (unsigned long long)attempts);
+      atomicAdd(&p.stats[1], (unsigned long long)accepted);
+      atomicAdd(&p.stats[2], (unsigned long long)(attempts - accepted));
+    }
   };
   if (have) init(cell);
 
@@ -294,6 +301,147 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
   }
 }
 
+
+// ------------------------------------------------------------------ one-wavefront-per-cell integrator
+__global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PERSISTENT) {
+  extern __shared__ double lds_raw[];
+  const MechView& M = p.M;
+  const int N = M.N, K = M.K, ldj = N + 1;
+  const int lane = threadIdx.x;
+  TeamLds L;
+  L.bind(lds_raw, N);
+  int64_t cell;
+  if (PERSISTENT) {
+    unsigned c0 = 0;
+    if (lane == 0) c0 = atomicAdd(p.queue, 1u);
+    cell = __shfl((int)c0, 0, 64);
+  } else {
+    cell = blockIdx.x;
+  }
+  while (cell < p.n) {
+    // ---- input conversion (eq. (conc_form1)), element i of Phi in lane i
+    const double P = p.P[cell];
+    const double T0 = p.T_in[cell];
+    double yk = 0.0;
+    if (lane < K) yk = p.Y_in[(int64_t)lane * p.ldY + cell] / M.W[lane];
+    const double inv = wave_sum(yk);
+    const double ysh = gather(yk, lane >= 2 ? lane - 2 : 0);
+    double phi = 0.0;
+    if (lane == 0) phi = T0;
+    if (lane == 1) phi = RU * T0 * inv / P;
+    if (lane >= 2 && lane < N) phi = ysh;
+    double rem = p.dt, h = p.dt;
+    if (p.h_io && p.h_io[cell] > 0.0) h = p.h_io[cell];
+    int attempts = 0, accepted = 0, bad = 0, status = 0;
+    bool last_rej = false, need_jac = true;
+    bool done = (p.T_cut > 0.0) && !(T0 >= p.T_cut);
+    const int64_t ck_rec = p.ck_off ? p.ck_off[cell] : 0;
+    double f1 = 0.0;
+    while (!done) {
+      if (attempts >= p.max_steps) {
+        status = CHEM_CELL_MAX_STEPS;
+        break;
+      }
+      if (h < p.h_min) {
+        status = CHEM_CELL_H_MIN;
+        break;
+      }
+      ++attempts;
+      const double hs = fmin(h, rem);
+      if (need_jac) {
+        f1 = team_rhs_jac(M, P, phi, L, p.lnA);
+        need_jac = false;
+      }
+      // M = I/(h gamma) - J in place of J (J is re-evaluated after a rejection)
+      const double d = 1.0 / (hs * ROS4_GAMMA);
+      if (lane < N)
+        for (int i = 0; i < N; ++i) L.J[i * ldj + lane] = (i == lane ? d : 0.0) - L.J[i * ldj + lane];
+      need_jac = true;
+      wsync();
+      int perm;
+      double rdiag;
+      const int rc = team_lu(L.J, ldj, N, perm, rdiag);
+      double err = 0.0, ynew = 0.0;
+      if (rc == 0) {
+        const double ih = 1.0 / hs;
+        const double* F = L.J;
+        const double u1 = team_solve(F, ldj, N, perm, rdiag, f1);
+        double fs = team_rhs(M, P, phi + ROS4_A21 * u1, L, p.lnA);
+        const double u2 = team_solve(F, ldj, N, perm, rdiag, fs + (ROS4_C21 * ih) * u1);
+        fs = team_rhs(M, P, phi + ROS4_A31 * u1 + ROS4_A32 * u2, L, p.lnA);
+        const double u3 = team_solve(F, ldj, N, perm, rdiag, fs + (ROS4_C31 * u1 + ROS4_C32 * u2) * ih);
+        const double u4 = team_solve(F, ldj, N, perm, rdiag,
+                                           fs + (ROS4_C41 * u1 + ROS4_C42 * u2 + ROS4_C43 * u3) * ih);
+        ynew = phi + ROS4_M1 * u1 + ROS4_M2 * u2 + ROS4_M3 * u3 + ROS4_M4 * u4;
+        const double e = ROS4_E1 * u1 + ROS4_E2 * u2 + ROS4_E3 * u3 + ROS4_E4 * u4;
+        const double sc = p.atol + p.rtol * fmax(fabs(phi), fabs(ynew));
+        const double r = (lane < N) ? e / sc : 0.0;
+        err = sqrt(wave_sum(r * r) / N);
+      }
+      if (rc != 0 || !isfinite(err)) {
+        if (++bad >= 10) {
+          status = (rc == 1) ? CHEM_CELL_SINGULAR : CHEM_CELL_NONFINITE;
+          break;
+        }
+        h = hs * p.fac_min;
+        last_rej = true;
+        continue;
+      }
+      bad = 0;
+      double fac = (err > 0.0) ? p.safety * pow(err, -0.25) : p.fac_max;
+      if (err <= 1.0) {
+        if (p.ck_data) {
+          double* rec = p.ck_data + (ck_rec + accepted) * (int64_t)(N + 1);
+          if (lane < N) rec[lane] = phi;
+          if (lane == 0) rec[N] = hs;
+        }
+        phi = ynew;
+        rem -= hs;
+        ++accepted;
+        fac = fmin(p.fac_max, fmax(p.fac_min, fac));
+        if (last_rej) fac = fmin(fac, 1.0);
+        last_rej = false;
+        h = hs * fac;
+        if (rem <= 0.0) break;
+      } else {
+        fac = fmin(1.0, fmax(p.fac_min, fac));
+        last_rej = true;
+        h = hs * fac;
+      }
+    }
+    // ---- output conversion: n_K from the ideal-gas closure, Y_k = n_k W_k / mass
+    {
+      const double T = bcast(phi, 0), V = bcast(phi, 1);
+      const double nk = gather(phi, lane + 2 < 64 ? lane + 2 : 0);
+      const double n_here = (lane < K - 1) ? nk : 0.0;
+      const double s = wave_sum(n_here);
+      const double nb = P * V / (RU * T) - s;
+      const double nn = (lane < K - 1) ? n_here : (lane == K - 1 ? nb : 0.0);
+      const double mass = wave_sum(lane < K ? nn * M.W[lane] : 0.0);
+      if (lane < K) p.Y_out[(int64_t)lane * p.ldY + cell] = nn * M.W[lane] / mass;
+      if (lane == 0) {
+        p.T_out[cell] = T;
+        if (p.h_io) p.h_io[cell] = h;
+        if (p.n_steps) p.n_steps[cell] = accepted;
+        if (p.status) p.status[cell] = status;
+        if (p.ck_count) p.ck_count[cell] = accepted;
+        if (p.stats) {
+          atomicAdd(&p.stats[0], (unsigned long long)attempts);
+          atomicAdd(&p.stats[1], (unsigned long long)accepted);
+          atomicAdd(&p.stats[2], (unsigned long long)(attempts - accepted));
+        }
+      }
+    }
+    if (PERSISTENT) {
+      unsigned c1 = 0;
+      if (lane == 0) c1 = atomicAdd(p.queue, 1u);
+      cell = __shfl((int)c1, 0, 64);
+    } else {
+      break;
+    }
+  }
+}
+
 // f and J at given states, for tests of the pieces.
 __global__ void eval_kernel(MechView M, int64_t n, const double* __restrict__ phi_in, int64_t ldp,
                             const double* __restrict__ P, const double* __restrict__ lnA,
@@ -383,6 +531,11 @@ int get_workspace(chem_mech_t m, hipStream_t s, int64_t slots, Workspace** out) 
   std::lock_guard<std::mutex> g(m->mu);
   Workspace& w = m->ws[s];
   const WsLayout L{m->view.N, m->view.K};
+  if (slots == 0) {
+    if (!w.queue && hipMalloc(&w.queue, 256) != hipSuccess) return CHEM_ENOMEM;
+    *out = &w;
+    return CHEM_OK;
+  }
   int rc = grow((void**)&w.ws, &w.ws_bytes, (size_t)L.total() * slots * sizeof(double));
   if (rc) return rc;
   rc = grow((void**)&w.piv, &w.piv_bytes, (size_t)m->view.N * slots * sizeof(int32_t));
@@ -395,6 +548,11 @@ int get_workspace(chem_mech_t m, hipStream_t s, int64_t slots, Workspace** out) 
 }
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+typedef void (*TeamKernel)(IntParams, bool);
+
+// One wavefront per cell holds a state vector element per lane: N <= 64.
+TeamKernel team_kernel(int N) { return N <= 64 ? integrate_team_kernel : nullptr; }
 
 }  // namespace
 
@@ -413,6 +571,7 @@ void chem_opts_default(chem_opts* o) {
   o->mode = CHEM_MODE_PLAIN;
   o->wg_size = 0;
   o->waves_per_cu = 0;
+  o->stats = nullptr;
 }
 
 const char* chem_error_string(int code) {
@@ -437,6 +596,7 @@ int chem_mech_load(const char* path, int device, chem_mech_t* out) {
     delete m;
     return rc;
   }
+  group_reactions_by_type(m->host);
   if (hipSetDevice(device) != hipSuccess) {
     delete m;
     return CHEM_EHIP;
@@ -456,7 +616,7 @@ int chem_mech_load(const char* path, int device, chem_mech_t* out) {
       {h.rinfo.data(), h.rinfo.size() * 4, 0},  {h.rspec.data(), h.rspec.size() * 4, 0},
       {h.rnu.data(), h.rnu.size() * 4, 0},      {h.arr.data(), h.arr.size() * 8, 0},
       {h.eff_idx.data(), h.eff_idx.size() * 4, 0}, {h.eff_am1.data(), h.eff_am1.size() * 8, 0},
-      {h.fo.data(), h.fo.size() * 8, 0}};
+      {h.fo.data(), h.fo.size() * 8, 0},         {h.rorig.data(), h.rorig.size() * 4, 0}};
   size_t total = 0;
   for (auto& p : parts) {
     p.off = total;
@@ -488,6 +648,7 @@ int chem_mech_load(const char* path, int device, chem_mech_t* out) {
   v.eff_idx = (const int32_t*)(b + parts[6].off);
   v.eff_am1 = (const double*)(b + parts[7].off);
   v.fo = (const double*)(b + parts[8].off);
+  v.rorig = (const int32_t*)(b + parts[9].off);
   *out = m;
   return CHEM_OK;
 }
@@ -545,7 +706,57 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   if (ckpt_out) *ckpt_out = nullptr;
   if (n == 0) return CHEM_OK;
   HIPCHECK(hipSetDevice(m->device));
-  const bool persistent = (o.mode == CHEM_MODE_PERSISTENT || o.mode == CHEM_MODE_TEAM_PERSISTENT);
+  int mode = o.mode;
+  if (mode == CHEM_MODE_AUTO) mode = (m->view.N <= 64) ? CHEM_MODE_TEAM_PERSISTENT : CHEM_MODE_PERSISTENT;
+  // one wavefront per cell needs N <= 64; larger mechanisms use one cell per thread
+  if (m->view.N > 64 && mode == CHEM_MODE_TEAM) mode = CHEM_MODE_PLAIN;
+  if (m->view.N > 64 && mode == CHEM_MODE_TEAM_PERSISTENT) mode = CHEM_MODE_PERSISTENT;
+  const bool persistent = (mode == CHEM_MODE_PERSISTENT || mode == CHEM_MODE_TEAM_PERSISTENT);
+  const bool team = (mode == CHEM_MODE_TEAM || mode == CHEM_MODE_TEAM_PERSISTENT);
+  if (team) {
+    Workspace* w;
+    int rc = get_workspace(m, stream, 0, &w);
+    if (rc) return rc;
+    IntParams p;
+    memset(&p, 0, sizeof(p));
+    p.M = m->view;
+    p.n = n;
+    p.T_in = T_in;
+    p.P = P;
+    p.Y_in = Y_in;
+    p.ldY = ldY;
+    p.T_out = T_out;
+    p.Y_out = Y_out;
+    p.dt = dt;
+    p.rtol = rtol;
+    p.atol = atol;
+    p.h_min = o.h_min;
+    p.safety = o.safety;
+    p.fac_min = o.fac_min;
+    p.fac_max = o.fac_max;
+    p.T_cut = o.T_cut;
+    p.max_steps = o.max_steps;
+    p.h_io = h_io;
+    p.n_steps = n_steps;
+    p.status = status;
+    p.lnA = lnA;
+    p.queue = w->queue;
+    p.stats = o.stats;
+    TeamKernel kern = team_kernel(m->view.N);
+    const size_t lds = TeamLds::doubles(m->view.N) * sizeof(double);
+    unsigned grid = (unsigned)n;
+    if (persistent) {
+      int per_cu = 0;
+      HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds));
+      if (o.waves_per_cu > 0) per_cu = std::min(per_cu, o.waves_per_cu);
+      if (per_cu < 1) per_cu = 1;
+      grid = (unsigned)std::min<int64_t>((int64_t)m->n_cu * per_cu, n);
+      hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, w->queue);
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, stream, p, persistent);
+    HIPCHECK(hipGetLastError());
+    return CHEM_OK;
+  }
   const int wg = o.wg_size ? o.wg_size : 64;
   int64_t slots;
   if (persistent) {
@@ -587,6 +798,7 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   p.piv = w->piv;
   p.ld = slots;
   p.queue = w->queue;
+  p.stats = o.stats;
   p.ck_data = nullptr;
   p.ck_off = nullptr;
   p.ck_count = nullptr;

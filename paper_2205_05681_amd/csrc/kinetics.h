@@ -102,7 +102,7 @@ __device__ __forceinline__ RateOut reaction_rate(const MechView& M, int j, doubl
   const int32_t* nu = M.rnu + 6 * j;
   const double* ar = M.arr + 4 * j;
   const int type = info[0], nr = info[1], np = info[2];
-  const double lnA = lnA_over ? lnA_over[j] : ar[0];
+  const double lnA = lnA_over ? lnA_over[M.rorig[j]] : ar[0];
   const double b = ar[1], th = ar[2], dnu = ar[3];
   const double lnkinf = lnA + b * lnT - th * iT;
   const double kinf = exp(lnkinf);

@@ -111,7 +111,26 @@ int parse_mechanism(const char* path, HostMech& m) {
     }
   }
   if (in.fail()) return CHEM_EPARSE;
+  m.rorig.resize(m.Nr);
+  for (int j = 0; j < m.Nr; ++j) m.rorig[j] = j;
   return CHEM_OK;
+}
+
+void group_reactions_by_type(HostMech& m) {
+  std::vector<int32_t> order;
+  for (int t = RX_ELEM; t <= RX_TROE; ++t)
+    for (int j = 0; j < m.Nr; ++j)
+      if (m.rinfo[(size_t)j * 8] == t) order.push_back(j);
+  HostMech r = m;
+  for (int jn = 0; jn < m.Nr; ++jn) {
+    const int j = order[jn];
+    for (int i = 0; i < 8; ++i) r.rinfo[(size_t)jn * 8 + i] = m.rinfo[(size_t)j * 8 + i];
+    for (int i = 0; i < 6; ++i) r.rspec[(size_t)jn * 6 + i] = m.rspec[(size_t)j * 6 + i];
+    for (int i = 0; i < 6; ++i) r.rnu[(size_t)jn * 6 + i] = m.rnu[(size_t)j * 6 + i];
+    for (int i = 0; i < 4; ++i) r.arr[(size_t)jn * 4 + i] = m.arr[(size_t)j * 4 + i];
+  }
+  r.rorig = order;
+  m = r;
 }
 
 }  // namespace chem

@@ -28,6 +28,7 @@ struct MechView {
   const int32_t* eff_idx;    // [n_eff]
   const double* eff_am1;     // [n_eff]: alpha - 1
   const double* fo;          // [n_fo][8]: lnA0 - lnA, b0, theta0, a, T3, T1, T2, 0
+  const int32_t* rorig;      // [Nr]: file index of internal reaction j (ln A override, gradients)
 };
 
 struct HostMech {
@@ -37,7 +38,13 @@ struct HostMech {
   std::vector<int32_t> comp;
   std::vector<int32_t> rinfo, rspec, rnu, eff_idx;
   std::vector<double> arr, eff_am1, fo;
+  std::vector<int32_t> rorig;   // file index of internal reaction j
 };
+
+// Groups reactions by type (elementary, third body, Lindemann, Troe) keeping
+// file order inside a group, so that the lanes of a wavefront walking the
+// reaction list mostly take the same branch.  rorig records the permutation.
+void group_reactions_by_type(HostMech& m);
 
 // Returns 0, or a CHEM_E* code.
 int parse_mechanism(const char* path, HostMech& m);

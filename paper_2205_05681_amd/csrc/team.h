@@ -1,0 +1,452 @@
+// One wavefront per cell ("team" kernels).
+//
+// Layout inside a wavefront (64 lanes, N = K + 1 <= NMAX <= 64):
+//   * element i of every state-sized vector (Phi, f, u_1..u_4, ...) lives in
+//     lane i, one register each;
+//   * row i of the iteration matrix M = I/(h gamma) - J lives in lane i as
+//     NMAX registers; the LU runs with implicit partial pivoting (rows stay in
+//     their lanes, the pivot order is recorded), the pivot search is a wave
+//     max-reduction plus a ballot, the pivot row is broadcast through LDS;
+//   * reactions are spread over lanes (reaction j on lane j mod 64); their
+//     contributions to the production rates and to the Jacobian are scattered
+//     into LDS with FP64 LDS atomics, then the chain rule through C(Phi) is
+//     applied in one row-parallel and one column-parallel pass;
+//   * every controller decision is uniform over the wavefront.
+// Work-groups are one wavefront, so a work-group barrier is a wave barrier.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kinetics.h"
+#include "mech.h"
+#include "ros4.h"
+
+namespace chem {
+
+__device__ __forceinline__ void wsync() { __syncthreads(); }
+
+// Value of lane `src` (wave-uniform) through two v_readlane.
+__device__ __forceinline__ double bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Value of lane `src` for a per-lane source (LDS crossbar).
+__device__ __forceinline__ double gather(double v, int src) { return __shfl(v, src, 64); }
+
+// Cross-lane move inside 16-lane rows (DPP); CTRL is the DPP control word.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_QUAD_1032 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_2301 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_MIRROR = 0x140;
+
+// Sum over the 64 lanes (all lanes must be active), the same value in every
+// lane: pairs, quads, octets and rows by DPP, then the four rows by readlane.
+// The association order is fixed, so the result is deterministic.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp<DPP_QUAD_1032>(v);
+  v += dpp<DPP_QUAD_2301>(v);
+  v += dpp<DPP_ROW_HALF_MIRROR>(v);
+  v += dpp<DPP_ROW_MIRROR>(v);
+  return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp<DPP_QUAD_1032>(v));
+  v = fmax(v, dpp<DPP_QUAD_2301>(v));
+  v = fmax(v, dpp<DPP_ROW_HALF_MIRROR>(v));
+  v = fmax(v, dpp<DPP_ROW_MIRROR>(v));
+  return fmax(fmax(bcast(v, 0), bcast(v, 16)), fmax(bcast(v, 32), bcast(v, 48)));
+}
+
+// Per-wavefront LDS scratch.  ldj = N + 1 (odd row stride in doubles).
+struct TeamLds {
+  double* J;      // [N][ldj]   Jacobian being assembled / kept for re-factorisation
+  double* brow;   // [ldj]      bath-gas row of d wdot / d Phi
+  double* conc;   // [64]
+  double* hrt;    // [64]
+  double* cpr;    // [64]
+  double* gib;    // [64]
+  double* wdot;   // [64]
+  double* gb;     // [64]      G column of the bath gas
+  double* tb;     // [64]      uniform third-body part per row
+  double* dwdT;   // [64]
+  double* dwdV;   // [64]
+  double* vec;    // [64]      staging of a lane-distributed vector
+  double* prow;   // [2][64]   pivot-row broadcast (double buffered)
+  int* plane;     // [64]      lane holding the k-th pivot row
+  static __host__ __device__ size_t doubles(int N) {
+    const int ldj = N + 1;
+    return (size_t)N * ldj + ldj + 11 * 64 + 128 + 32;
+  }
+  __device__ void bind(double* base, int N) {
+    const int ldj = N + 1;
+    J = base;
+    brow = J + (size_t)N * ldj;
+    conc = brow + ldj;
+    hrt = conc + 64;
+    cpr = hrt + 64;
+    gib = cpr + 64;
+    wdot = gib + 64;
+    gb = wdot + 64;
+    tb = gb + 64;
+    dwdT = tb + 64;
+    dwdV = dwdT + 64;
+    vec = dwdV + 64;
+    prow = vec + 64;
+    plane = (int*)(prow + 128);
+  }
+};
+
+// Lane-distributed LDS view with a fixed stride, to reuse reaction_rate().
+struct LdsLane {
+  double* p;
+  __device__ __forceinline__ double& operator[](int i) const { return p[i]; }
+};
+
+// Concentrations and thermo of the state y (lane-distributed, element i in
+// lane i).  Returns (T, V, sum C) uniform; fills conc/hrt/cpr/gib in LDS.
+// sdcp (optional) receives sum_k C_k dcp_k/dT / R.
+__device__ __forceinline__ void team_state(const MechView& M, double P, double y, TeamLds& L,
+                                           double& T, double& V, double& ctot, double* sdcp) {
+  const int lane = threadIdx.x;
+  const int K = M.K;
+  T = bcast(y, 0);
+  V = bcast(y, 1);
+  L.vec[lane] = y;
+  wsync();
+  double c = 0.0;
+  if (lane < K - 1) c = L.vec[lane + 2] / V;
+  const double s = wave_sum(c);
+  if (lane == K - 1) c = P / (RU * T) - s;
+  ctot = wave_sum(c);
+  if (lane < K) L.conc[lane] = c;
+  double dcp = 0.0;
+  if (lane < K) {
+    const double* cf = M.nasa + 15 * lane;
+    const bool lo = T < cf[0];
+    const double a0 = lo ? cf[1] : cf[8], a1 = lo ? cf[2] : cf[9], a2 = lo ? cf[3] : cf[10],
+                 a3 = lo ? cf[4] : cf[11], a4 = lo ? cf[5] : cf[12], a5 = lo ? cf[6] : cf[13],
+                 a6 = lo ? cf[7] : cf[14];
+    const double lnT = log(T), iT = 1.0 / T;
+    const double cp = a0 + T * (a1 + T * (a2 + T * (a3 + T * a4)));
+    const double h = a0 + T * (a1 * 0.5 + T * (a2 * (1.0 / 3.0) + T * (a3 * 0.25 + T * a4 * 0.2))) + a5 * iT;
+    const double sr = a0 * lnT + T * (a1 + T * (a2 * 0.5 + T * (a3 * (1.0 / 3.0) + T * a4 * 0.25))) + a6;
+    L.hrt[lane] = h;
+    L.cpr[lane] = cp;
+    L.gib[lane] = sr - h;
+    if (sdcp) dcp = c * (a1 + T * (2.0 * a2 + T * (3.0 * a3 + T * 4.0 * a4)));
+  }
+  if (sdcp) *sdcp = wave_sum(dcp);
+  wsync();
+}
+
+// f(y) for lane-distributed y; returns f_i in lane i.
+__device__ double team_rhs(const MechView& M, double P, double y, TeamLds& L,
+                           const double* __restrict__ lnA) {
+  const int lane = threadIdx.x;
+  const int K = M.K, N = M.N;
+  double T, V, ctot;
+  team_state(M, P, y, L, T, V, ctot, nullptr);
+  if (lane < K) L.wdot[lane] = 0.0;
+  wsync();
+  const double lnT = log(T), iT = 1.0 / T;
+  LdsLane conc{L.conc}, gib{L.gib}, hrt{L.hrt};
+  for (int j = lane; j < M.Nr; j += 64) {
+    const RateOut r = reaction_rate(M, j, T, lnT, iT, ctot, Lane{conc.p, 1}, Lane{gib.p, 1},
+                                    Lane{hrt.p, 1}, lnA, false);
+    const int32_t* info = M.rinfo + 8 * j;
+    const int32_t* sp = M.rspec + 6 * j;
+    const int32_t* nu = M.rnu + 6 * j;
+    for (int i = 0; i < info[1]; ++i) atomicAdd(&L.wdot[sp[i]], -nu[i] * r.q);
+    for (int i = 0; i < info[2]; ++i) atomicAdd(&L.wdot[sp[3 + i]], nu[3 + i] * r.q);
+  }
+  wsync();
+  double w = 0.0, num = 0.0, den = 0.0;
+  if (lane < K) {
+    w = L.wdot[lane];
+    num = L.hrt[lane] * w;
+    den = L.conc[lane] * L.cpr[lane];
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  const double ws = wave_sum(w);
+  const double Tdot = -(num * T) / den;
+  double f = 0.0;
+  if (lane == 0) f = Tdot;
+  if (lane == 1) f = V * (Tdot * iT + (RU * T / P) * ws);
+  if (lane >= 2 && lane < N) f = V * L.wdot[lane - 2];
+  wsync();
+  return f;
+}
+
+// f(y) and the Jacobian, assembled in L.J (row i at L.J[i*(N+1)]).
+__device__ double team_rhs_jac(const MechView& M, double P, double y, TeamLds& L,
+                               const double* __restrict__ lnA) {
+  const int lane = threadIdx.x;
+  const int K = M.K, N = M.N, ldj = N + 1;
+  double T, V, ctot, sdcp;
+  team_state(M, P, y, L, T, V, ctot, &sdcp);
+  const double lnT = log(T), iT = 1.0 / T, iV = 1.0 / V;
+  // clear: column `lane` of every species row, the bath row and the per-row sums
+  if (lane < N) {
+    for (int k = 0; k < K - 1; ++k) L.J[(k + 2) * ldj + lane] = 0.0;
+    L.brow[lane] = 0.0;
+  }
+  if (lane < K) {
+    L.wdot[lane] = 0.0;
+    L.gb[lane] = 0.0;
+    L.tb[lane] = 0.0;
+  }
+  wsync();
+  for (int j = lane; j < M.Nr; j += 64) {
+    const RateOut r = reaction_rate(M, j, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
+                                    Lane{L.hrt, 1}, lnA, true);
+    const int32_t* info = M.rinfo + 8 * j;
+    const int32_t* sp = M.rspec + 6 * j;
+    const int32_t* nu = M.rnu + 6 * j;
+    const int nr = info[1], np = info[2];
+    const double dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
+    double dq[6];
+    int ms[6];
+    int nm = 0;
+    for (int i = 0; i < nr; ++i) {
+      double d = r.kf;
+      for (int l = 0; l < nr; ++l) {
+        const double c = L.conc[sp[l]];
+        const int v = (l == i) ? nu[l] - 1 : nu[l];
+        if (v >= 1) d *= c;
+        if (v >= 2) d *= c;
+        if (v >= 3) d *= c;
+      }
+      ms[nm] = sp[i];
+      dq[nm++] = d * nu[i];
+    }
+    for (int i = 0; i < np; ++i) {
+      double d = r.kr;
+      for (int l = 0; l < np; ++l) {
+        const double c = L.conc[sp[3 + l]];
+        const int v = (l == i) ? nu[3 + l] - 1 : nu[3 + l];
+        if (v >= 1) d *= c;
+        if (v >= 2) d *= c;
+        if (v >= 3) d *= c;
+      }
+      ms[nm] = sp[3 + i];
+      dq[nm++] = -d * nu[3 + i];
+    }
+    for (int side = 0; side < 2; ++side) {
+      const int cnt = side ? np : nr;
+      for (int i = 0; i < cnt; ++i) {
+        const int k = sp[3 * side + i];
+        const double vk = side ? (double)nu[3 + i] : -(double)nu[i];
+        double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+        atomicAdd(&L.wdot[k], vk * r.q);
+        atomicAdd(&row[0], vk * dqdT);
+        for (int t = 0; t < nm; ++t) {
+          const int m = ms[t];
+          atomicAdd((m == K - 1) ? &L.gb[k] : &row[m + 2], vk * dq[t]);
+        }
+        if (info[0] != RX_ELEM) {
+          atomicAdd(&L.tb[k], vk * r.beta);
+          for (int e = info[3]; e < info[4]; ++e) {
+            const int m = M.eff_idx[e];
+            atomicAdd((m == K - 1) ? &L.gb[k] : &row[m + 2], vk * M.eff_am1[e] * r.beta);
+          }
+        }
+      }
+    }
+  }
+  wsync();
+  // pass 1, row-parallel (lane k = species row): Phi coordinates of row k
+  const double dCb_dT = -P / (RU * T * T);
+  double num = 0.0, den = 0.0, wsum = 0.0, wcp = 0.0, dDV = 0.0;
+  if (lane < K) {
+    const int k = lane;
+    double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+    const double t = L.tb[k];
+    const double gbk = L.gb[k] + t;
+    const double wk = L.wdot[k];
+    const double cpk = L.cpr[k] * RU;
+    num = L.hrt[k] * RU * T * wk;
+    den = L.conc[k] * cpk;
+    wsum = wk;
+    wcp = wk * cpk;
+    double dvs = 0.0;
+    for (int m = 0; m < K - 1; ++m) {
+      const double dn = row[m + 2] + t - gbk;
+      dvs -= dn * L.conc[m];
+      row[m + 2] = dn;
+    }
+    const double dwdT = row[0] + gbk * dCb_dT;
+    L.dwdT[k] = dwdT;
+    L.dwdV[k] = dvs * iV;
+    if (k < K - 1) {
+      row[0] = V * dwdT;
+      row[1] = wk + dvs;
+      dDV = (L.cpr[K - 1] - L.cpr[k]) * RU * L.conc[k];
+    }
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  wsum = wave_sum(wsum);
+  wcp = wave_sum(wcp);
+  dDV = wave_sum(dDV) * iV;
+  wsync();
+  // pass 2, column-parallel (lane c = column): the T and V rows
+  const double Tdot = -num / den;
+  const double RTP = RU * T / P;
+  if (lane < N) {
+    const int c = lane;
+    double ah = 0.0, aw = 0.0;
+    if (c >= 2) {
+      for (int k = 0; k < K; ++k) {
+        const double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+        const double d = row[c] * iV;           // d wdot_k / d n_m
+        ah += L.hrt[k] * RU * T * d;
+        aw += d;
+      }
+    } else {
+      const double* src = (c == 0) ? L.dwdT : L.dwdV;
+      for (int k = 0; k < K; ++k) {
+        const double d = src[k];
+        ah += L.hrt[k] * RU * T * d;
+        aw += d;
+      }
+    }
+    const double cpb = L.cpr[K - 1] * RU;
+    double dD, dTd, dVd;
+    if (c == 0) {
+      dD = sdcp * RU + cpb * dCb_dT;
+      dTd = -(ah + wcp) / den - Tdot * dD / den;
+      dVd = V * dTd * iT - V * Tdot * iT * iT + (RU * V / P) * wsum + RTP * V * aw;
+    } else if (c == 1) {
+      dD = dDV;
+      dTd = -ah / den - Tdot * dD / den;
+      dVd = Tdot * iT + V * dTd * iT + RTP * wsum + RTP * V * aw;
+    } else {
+      dD = (L.cpr[c - 2] * RU - cpb) * iV;
+      dTd = -ah / den - Tdot * dD / den;
+      dVd = V * dTd * iT + RTP * V * aw;
+    }
+    L.J[c] = dTd;
+    L.J[ldj + c] = dVd;
+  }
+  double f = 0.0;
+  if (lane == 0) f = Tdot;
+  if (lane == 1) f = V * (Tdot * iT + RTP * wsum);
+  if (lane >= 2 && lane < N) f = V * L.wdot[lane - 2];
+  wsync();
+  return f;
+}
+
+// In-place LU with partial pivoting of the N x N matrix held in LDS (row i at
+// F[i * ldj]); rows are swapped explicitly so that, as in a textbook LU, the
+// pivot of column k is the largest |F[i][k]|, i >= k, ties to the lowest row.
+// The multipliers of column k are computed by lanes over rows and reach the
+// trailing update (lanes over columns) through v_readlane, so the update loop
+// only reads and writes its own column, eight rows at a time.
+// perm (lane-distributed) receives the row permutation: row i of the factors
+// is original row perm[i]; rdiag (lane-distributed) receives 1 / U_ii.
+// Returns 0, 1 (zero pivot) or 2 (non-finite column).
+__device__ __forceinline__ int team_lu(double* __restrict__ F, int ldj, int N, int& perm,
+                                       double& rdiag) {
+  const int lane = threadIdx.x;
+  perm = lane;
+  rdiag = 0.0;
+  for (int k = 0; k < N; ++k) {
+    // pivot search, lanes over rows
+    double a = -1.0;
+    if (lane >= k && lane < N) a = fabs(F[lane * ldj + k]);
+    if (__any(lane >= k && lane < N && !isfinite(a))) return 2;
+    const double best = wave_max(a);
+    if (!(best > 0.0)) return 1;
+    const int p = __builtin_amdgcn_readfirstlane(__ffsll((long long)__ballot(a == best)) - 1);
+    if (p != k) {
+      if (lane < N) {
+        const double t = F[k * ldj + lane];
+        F[k * ldj + lane] = F[p * ldj + lane];
+        F[p * ldj + lane] = t;
+      }
+      const int pk = __builtin_amdgcn_readlane(perm, k), pp = __builtin_amdgcn_readlane(perm, p);
+      if (lane == k) perm = pp;
+      if (lane == p) perm = pk;
+      wsync();
+    }
+    // multipliers, lanes over rows (held in lmul for the broadcast)
+    const double ukk = F[k * ldj + k];
+    const double rk = 1.0 / ukk;
+    if (lane == k) rdiag = rk;
+    double lmul = 0.0;
+    if (lane > k && lane < N) {
+      lmul = F[lane * ldj + k] / ukk;
+      F[lane * ldj + k] = lmul;
+    }
+    // trailing update, lanes over columns j > k, rows in chunks of 8
+    const bool col_active = lane > k && lane < N;
+    const double ukj = col_active ? F[k * ldj + lane] : 0.0;
+    double* col = F + lane;
+    for (int i0 = k + 1; i0 < N; i0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        v[t] = (col_active && i0 + t < N) ? col[(i0 + t) * ldj] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int i = i0 + t < N ? i0 + t : N - 1;
+        v[t] -= bcast(lmul, i) * ukj;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (col_active && i0 + t < N) col[(i0 + t) * ldj] = v[t];
+    }
+    wsync();
+  }
+  return 0;
+}
+
+// Solve M x = b with the factors of team_lu.  b and x are lane-distributed
+// (element i in lane i).
+__device__ __forceinline__ double team_solve(const double* __restrict__ F, int ldj, int N, int perm,
+                                             double rdiag, double b) {
+  const int lane = threadIdx.x;
+  const double* row = F + (lane < N ? lane : 0) * ldj;
+  b = gather(b, perm);                       // P b
+  // forward, unit lower triangle; k is wave-uniform, so the broadcast is a readlane
+  for (int k0 = 0; k0 < N - 1; k0 += 8) {
+    double l[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) l[t] = (k0 + t < N) ? row[k0 + t] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + t;
+      if (k < N - 1) {
+        const double yk = bcast(b, k);
+        if (lane > k && lane < N) b -= l[t] * yk;
+      }
+    }
+  }
+  // backward, upper triangle
+  for (int k1 = N - 1; k1 >= 0; k1 -= 8) {
+    double u[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) u[t] = (k1 - t >= 0) ? row[k1 - t] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k1 - t;
+      if (k >= 0) {
+        const double xk = bcast(b, k) * bcast(rdiag, k);
+        if (lane == k) b = xk;
+        if (lane < k) b -= u[t] * xk;
+      }
+    }
+  }
+  return b;
+}
+
+}  // namespace chem

@@ -1,0 +1,85 @@
+"""Algorithmic operation counts of one ROS4 step for a given mechanism.
+
+The roofline of the integrator is priced in *algorithmic* FP64 operations:
+what the method needs, independent of how a kernel organises it.  Additions,
+subtractions, multiplications and divisions count 1, a fused multiply-add 2;
+exp/log/log10 are counted separately (they are not part of the flop count).
+
+Per attempted step the method needs (paper Sec. 2.3, one LU per step):
+  * M = I/(h gamma) - J and its LU with partial pivoting;
+  * four forward/backward substitutions;
+  * two new source-term evaluations (stages 2 and 3; stage 4 reuses 3);
+  * the stage combinations and the error norm.
+Per accepted step it also needs f and the analytical Jacobian at the new
+state; a rejected step reuses them.  So for a batch:
+  flops = accepted * F_fJ + attempts * (F_M + F_LU + 4 F_sol + 2 F_f + F_vec).
+"""
+from __future__ import annotations
+
+
+def _thermo(K, with_dcp):
+    # cp (8), h/RT (11), s/R (10), g = s - h (1); dcp/dT (8) for the Jacobian
+    return K * (30 + (8 if with_dcp else 0)) + 2
+
+
+def _reaction(r, jac):
+    nr, np_ = len(r.reac), len(r.prod)
+    nu_r = sum(n for _, n in r.reac)
+    nu_p = sum(n for _, n in r.prod)
+    f = 5                                       # ln k = lnA + b lnT - theta/T
+    if r.kind != "E":
+        f += 1 + 2 * len(r.eff)                 # [M]
+        f += 1 if r.kind == "T" else 0
+    if r.kind in "LF":
+        f += 5 + 3                              # k0, Pr, Pr/(1+Pr) k_inf
+    if r.kind == "F":
+        f += 12 + 10 + 2                        # Fcent, c, n, x, y, log F, F
+    f += 2 * (nr + np_) + 3                     # ln Kc, k_r
+    f += max(nu_r - 1, 0) + max(nu_p - 1, 0) + 3   # products and q
+    f += 2 * (nr + np_)                         # wdot scatter (FMA)
+    if jac:
+        f += 6                                  # dq/dT
+        f += (nr + np_) * (nr + np_)            # dq/dC of the participants
+        f += 2 * (nr + np_) * (1 + nr + np_)    # scatter into G and the T column
+        if r.kind != "E":
+            f += 4 + 2 * (nr + np_) * (1 + len(r.eff))
+        if r.kind == "F":
+            f += 30                             # Troe derivatives
+    return f
+
+
+def _transcendentals(r):
+    t = 1                                       # exp(ln k)
+    if r.kind in "LF":
+        t += 1
+    if r.kind == "F":
+        t += 3 + 2 + 1                          # three exp in Fcent, two log10, F
+    t += 1                                      # exp(-ln Kc)
+    return t
+
+
+def step_counts(mech):
+    """Dict of per-piece algorithmic flop counts for a synth.Mechanism."""
+    K = mech.n_species
+    N = K + 1
+    rx = mech.reactions
+    f_rhs = (2 * K + 3) + _thermo(K, False) + sum(_reaction(r, False) for r in rx) + 6 * K + 12 + K
+    f_fj = (2 * K + 3) + _thermo(K, True) + sum(_reaction(r, True) for r in rx) + 6 * K + 12 + K
+    f_fj += K * (K - 1) * 4 + K * 6                 # Phi coordinates of the species rows
+    f_fj += (N - 2) * K * 4 + N * 20 + (K - 1) * 3  # T and V rows
+    f_m = N * N + 2
+    f_lu = sum((N - k - 1) + 2 * (N - k - 1) ** 2 for k in range(N))
+    f_sol = N * (N - 1) + N * (N - 1) + N
+    f_vec = 30 * N + 3 * N + 2
+    t_rhs = sum(_transcendentals(r) for r in rx) + 2
+    return dict(N=N, rhs=f_rhs, rhs_jac=f_fj, matrix=f_m, lu=f_lu, solve=f_sol, vector=f_vec,
+                per_attempt=f_m + f_lu + 4 * f_sol + 2 * f_rhs + f_vec, per_accept=f_fj,
+                transcendentals_per_rhs=t_rhs)
+
+
+def batch_flops(mech, attempts, accepted):
+    """Algorithmic FP64 flops and transcendental calls of a batch."""
+    c = step_counts(mech)
+    flops = accepted * c["per_accept"] + attempts * c["per_attempt"]
+    trans = (accepted + 2 * attempts) * c["transcendentals_per_rhs"]
+    return flops, trans

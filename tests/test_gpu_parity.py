@@ -117,12 +117,13 @@ def test_rhs_and_jacobian_parity(chem, name, request):
     mech.close()
 
 
-def test_small_parity_full_config(chem, small):
+@pytest.mark.parametrize("mode", ["plain", "team_persistent"])
+def test_small_parity_full_config(chem, small, mode):
     path, m, o = small
-    say("case: small mechanism, 256 cells, plain")
+    say("case: small mechanism, 256 cells,", mode)
     T, P, Y = synth.states_small(m)
     mech = chem.Mechanism(path)
-    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6)
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
     r = o.integrate(T, P, Y, 1e-6)
     assert np.all(sg == 0) and np.all(r["status"] == 0)
     assert_parity(Tg, Yg, r["T"], r["Y"], "small", o, (T, P, Y), 1e-6)
@@ -135,7 +136,7 @@ def test_small_parity_full_config(chem, small):
     mech.close()
 
 
-@pytest.mark.parametrize("mode", ["plain", "persistent"])
+@pytest.mark.parametrize("mode", ["plain", "persistent", "team", "team_persistent"])
 def test_ch4_parity_ragged(chem, ch4, mode):
     """1,000 mixing-layer cells (15 full wavefronts and a ragged tail)."""
     path, m, o = ch4
@@ -156,22 +157,26 @@ def test_ch4_full_size_sampled(chem, ch4):
     """65,536 cells in the benchmark's launch; 96 cells re-run on the oracle,
     the hottest ones included."""
     path, m, o = ch4
-    say("case: ch4 mechanism, 65536 cells sampled, plain + persistent")
+    say("case: ch4 mechanism, 65536 cells sampled, all launch modes")
     T, P, Y = synth.states_mixing(m, 65536, 202)
     mech = chem.Mechanism(path)
     res = {}
-    for mode in ("plain", "persistent"):
-        res[mode] = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
-    # the two launches run the same per-cell arithmetic
-    assert np.array_equal(res["plain"][0], res["persistent"][0])
-    assert np.array_equal(res["plain"][1], res["persistent"][1])
-    Tg, Yg, hg, ng, sg = res["plain"]
+    for mode in ("plain", "persistent", "team", "team_persistent", "team_persistent"):
+        key = mode if mode not in res else mode + "2"
+        res[key] = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
+    # plain and persistent launches run the same per-cell arithmetic; so do the
+    # two team launches; a repeated launch is bit-identical
+    for a, b in (("plain", "persistent"), ("team", "team_persistent"), ("team_persistent", "team_persistent2")):
+        assert np.array_equal(res[a][0], res[b][0]), (a, b)
+        assert np.array_equal(res[a][1], res[b][1]), (a, b)
     rng = np.random.default_rng(0)
-    idx = np.unique(np.r_[rng.choice(65536, 64, replace=False), np.argsort(-ng)[:32]])
-    r = o.integrate(T[idx], P[idx], Y[:, idx].copy(), 1e-6)
-    assert_parity(Tg[idx], Yg[:, idx], r["T"], r["Y"], "ch4 full", o, (T[idx], P[idx], Y[:, idx]),
-                  1e-6, max_frac=0.03)
-    assert np.mean(ng[idx] == r["n_acc"]) >= 0.97
+    for mode in ("plain", "team_persistent"):
+        Tg, Yg, hg, ng, sg = res[mode]
+        idx = np.unique(np.r_[rng.choice(65536, 64, replace=False), np.argsort(-ng)[:32]])
+        r = o.integrate(T[idx], P[idx], Y[:, idx].copy(), 1e-6)
+        assert_parity(Tg[idx], Yg[:, idx], r["T"], r["Y"], "ch4 full " + mode, o,
+                      (T[idx], P[idx], Y[:, idx]), 1e-6, max_frac=0.03)
+        assert np.mean(ng[idx] == r["n_acc"]) >= 0.97
     mech.close()
 
 
