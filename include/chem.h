@@ -61,6 +61,7 @@ extern "C" {
 #define CHEM_MODE_TEAM_PERSISTENT 4 /* one wavefront per cell, resident grid, work queue */
 
 typedef struct chem_mech_s* chem_mech_t; /* opaque, library-owned */
+typedef struct chem_graph_s* chem_graph_t; /* opaque, library-owned captured split step */
 typedef struct chem_ckpt_s* chem_ckpt_t; /* opaque, library-owned adjoint checkpoint */
 
 /* Integration options.  Fill with chem_opts_default() and override. */
@@ -72,7 +73,7 @@ typedef struct {
   double fac_max;         /* largest step ratio (6) */
   double T_cut;           /* cells with T_in < T_cut are copied, not integrated (0 = off) */
   int32_t max_steps;      /* attempted steps per cell before CHEM_CELL_MAX_STEPS (100000) */
-  int32_t mode;           /* CHEM_MODE_* */
+  int32_t mode;           /* CHEM_MODE_* (CHEM_MODE_AUTO) */
   int32_t wg_size;        /* work-group size in threads (0 = library choice) */
   int32_t waves_per_cu;   /* persistent modes: resident waves per CU (0 = occupancy limit) */
   unsigned long long* stats; /* nullable DEVICE pointer to 3 counters that the call adds to:
@@ -106,9 +107,12 @@ void chem_mech_free(chem_mech_t m);
  *             move their low-pressure A by the same factor), for
  *             differentiation with respect to ln A
  *   opts      nullable (defaults)
- *   ckpt_out  nullable; non-null records every accepted step (state, h and
- *             the four stage vectors) for chem_integrate_adjoint; *ckpt_out
- *             receives a new checkpoint that the caller frees
+ *   ckpt_out  nullable; non-null records every accepted step (state and h;
+ *             the adjoint recomputes the stage vectors) for
+ *             chem_integrate_adjoint; *ckpt_out receives a new checkpoint
+ *             that the caller frees.  This runs the integration twice (a
+ *             counting pass sizes the record arena) and synchronises the
+ *             stream; the counting pass writes only library scratch
  * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM.  Asynchronous on `stream`. */
 int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const double* P,
                    const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
@@ -122,13 +126,58 @@ int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const dou
  *   g_lnA               [Nr] dL/d ln A summed over cells (per_cell = 0) or
  *                       [Nr][n] per cell (per_cell = 1), overwritten
  *   gT0[n], gY0[K][ldY] nullable: dL/dT_in, dL/dY_in
- * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM. */
+ * One wavefront per cell: needs N <= 64 and the per-cell LDS (two N x (N+1)
+ * matrices, dual vectors and Nr accumulators) within 64 KiB, else
+ * CHEM_EUNSUPPORTED.  The sum over cells is taken in a fixed order.
+ * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM, CHEM_EUNSUPPORTED. */
 int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, const double* gY,
                            int64_t ldY, double* g_lnA, int32_t per_cell, double* gT0,
                            double* gY0, hipStream_t stream);
 
 /* Release a checkpoint (synchronises its stream). */
 void chem_ckpt_free(chem_ckpt_t c);
+
+/* Number of records in a checkpoint: for each cell, one per accepted step
+ * plus one for the final state; -1 for a null handle. */
+int64_t chem_ckpt_records(chem_ckpt_t c);
+
+/* Copy a checkpoint to host memory (synchronises): off[n+1] record offsets of
+ * the cells (host), records[chem_ckpt_records][N+1] = (Phi_n, h_n) of each
+ * accepted step then (Phi_final, 0) per cell (host).  Either may be null.
+ * For inspection and tests. */
+int chem_ckpt_export(chem_ckpt_t c, int64_t* off, double* records);
+
+/* Autotuner.  Times the launch configurations (one wavefront per cell,
+ * plain or persistent with 1..4 resident waves per CU; and, for mechanisms
+ * with N <= 16, one cell per thread with 64- or 256-thread groups) on a
+ * stratified sample of up to 4096 cells of the given batch, two runs each,
+ * and keeps the fastest for this mechanism and the batch-size bucket
+ * floor(log2(n_cells)).  CHEM_MODE_AUTO then uses it.  The choice is kept
+ * with the handle and, when the environment variable CHEM_AUTOTUNE_CACHE
+ * names a file, appended there and read back by later handles of the same
+ * mechanism shape.  *chosen (nullable) receives the winning options; ms
+ * (nullable, 8 entries) the best time of each candidate in the order tried
+ * (unused entries -1).  Synchronises `stream`. */
+int chem_autotune(chem_mech_t m, int64_t n_cells, const double* T_in, const double* P,
+                  const double* Y_in, int64_t ldY, double dt, double rtol, double atol,
+                  chem_opts* chosen, double* ms, hipStream_t stream);
+
+/* Capture one split step - chem_integrate with exactly these arguments, no
+ * checkpoint - into a HIP graph (the work-queue reset is a kernel node, so
+ * the graph holds no memset node).  The pointers are baked in: a replay reads
+ * and writes the same buffers, so the caller refreshes the inputs (and h_io,
+ * which a step overwrites) between replays.  Replays of one graph must not
+ * overlap; the graph uses its own workspace.  Errors as chem_integrate. */
+int chem_graph_create(chem_mech_t m, int64_t n_cells, const double* T_in, const double* P,
+                      const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
+                      double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
+                      const double* lnA, const chem_opts* opts, chem_graph_t* out);
+
+/* Replay a captured split step on `stream` (asynchronous). */
+int chem_graph_launch(chem_graph_t g, hipStream_t stream);
+
+/* Release a captured split step (synchronises the device). */
+void chem_graph_free(chem_graph_t g);
 
 /* Evaluate the source terms f(Phi) (eq. (dphidt)) and, if J is non-null, the
  * dense Jacobian (eq. (jac)) for n cells.  phi[N][ld], f[N][ld],

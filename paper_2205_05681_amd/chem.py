@@ -57,13 +57,25 @@ def lib():
                                      C.POINTER(_vp), _vp]
         L.chem_integrate_adjoint.argtypes = [_vp, _vp, _vp, _vp, C.c_int64, _vp, C.c_int32, _vp, _vp, _vp]
         L.chem_ckpt_free.argtypes = [_vp]
+        L.chem_ckpt_records.restype = C.c_int64
+        L.chem_ckpt_records.argtypes = [_vp]
+        L.chem_ckpt_export.argtypes = [_vp, _vp, _vp]
+        L.chem_graph_create.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, C.c_int64, _vp, _vp, C.c_double,
+                                        C.c_double, C.c_double, _vp, _vp, _vp, _vp, C.POINTER(Opts),
+                                        C.POINTER(_vp)]
+        L.chem_graph_launch.argtypes = [_vp, _vp]
+        L.chem_autotune.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, C.c_int64, C.c_double, C.c_double,
+                                    C.c_double, C.POINTER(Opts), _vp, _vp]
+        L.chem_graph_free.argtypes = [_vp]
         L.chem_eval.argtypes = [_vp, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]
         _lib = L
     return _lib
 
 
 EXPORTS = ("chem_opts_default", "chem_error_string", "chem_mech_load", "chem_mech_info",
-           "chem_mech_free", "chem_integrate", "chem_integrate_adjoint", "chem_ckpt_free", "chem_eval")
+           "chem_mech_free", "chem_integrate", "chem_integrate_adjoint", "chem_ckpt_free", "chem_eval",
+           "chem_ckpt_records", "chem_ckpt_export", "chem_graph_create", "chem_graph_launch",
+           "chem_graph_free", "chem_autotune")
 
 
 def error_string(code):
@@ -138,10 +150,42 @@ class Mechanism:
             pass
 
 
+class Checkpoint:
+    """Accepted steps of a checkpointed integration (chem_ckpt_t)."""
+
+    def __init__(self, mech, handle, n):
+        self.mech, self.handle, self.n = mech, handle, n
+
+    def records(self):
+        return lib().chem_ckpt_records(self.handle)
+
+    def export(self):
+        """(offsets (n+1,), records (R, N+1)) on the host: per cell the accepted
+        (Phi_n, h_n), then (Phi_final, 0)."""
+        import numpy as np
+        off = np.zeros(self.n + 1, np.int64)
+        rec = np.zeros((self.records(), self.mech.N + 1))
+        _check(lib().chem_ckpt_export(self.handle, off.ctypes.data_as(C.c_void_p),
+                                      rec.ctypes.data_as(C.c_void_p)), "chem_ckpt_export")
+        return off, rec
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().chem_ckpt_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, h=None, lnA=None, opts=None,
-              out=None, n_steps=None, status=None):
+              out=None, n_steps=None, status=None, checkpoint=False):
     """Advance every cell over dt.  T, P: (n,); Y: (K, n) SoA.  Returns
-    (T1, Y1, h1, n_steps, status); h is updated in place when given."""
+    (T1, Y1, h1, n_steps, status), plus a Checkpoint when checkpoint=True; h
+    is updated in place when given."""
     n = T.numel()
     K = mech.K
     dev = T.device
@@ -160,14 +204,113 @@ def integrate(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, h=None, lnA=None, opts=N
     if status is None:
         status = torch.empty(n, dtype=torch.int32, device=dev)
     o = opts if opts is not None else default_opts()
+    ck = C.c_void_p() if checkpoint else None
     rc = lib().chem_integrate(mech.handle, n, pT, pP, pY, n, _ptr(T1, "T_out", shape=(n,)),
                               _ptr(Y1, "Y_out", shape=(K, n)), float(dt), float(rtol), float(atol),
                               _ptr(h, "h", shape=(n,)), _ptr(n_steps, "n_steps", torch.int32, (n,)),
                               _ptr(status, "status", torch.int32, (n,)),
-                              _ptr(lnA, "lnA", shape=(mech.Nr,), allow_none=True), C.byref(o), None,
-                              _stream())
+                              _ptr(lnA, "lnA", shape=(mech.Nr,), allow_none=True), C.byref(o),
+                              C.byref(ck) if checkpoint else None, _stream())
     _check(rc, "chem_integrate")
+    if checkpoint:
+        return T1, Y1, h, n_steps, status, Checkpoint(mech, ck, n)
     return T1, Y1, h, n_steps, status
+
+
+def adjoint(mech, ckpt, gT, gY, per_cell=False, initial=True):
+    """Discrete adjoint of a checkpointed integration.  gT (n,), gY (K, n) are
+    dL/dT_final and dL/dY_final.  Returns (g_lnA, gT0, gY0): g_lnA is (Nr,)
+    summed over cells, or (Nr, n) per cell; gT0, gY0 are the gradients with
+    respect to the initial T and Y (None unless initial)."""
+    n = ckpt.n
+    dev = gT.device
+    g = torch.empty((mech.Nr, n) if per_cell else (mech.Nr,), dtype=torch.float64, device=dev)
+    gT0 = torch.empty(n, dtype=torch.float64, device=dev) if initial else None
+    gY0 = torch.empty((mech.K, n), dtype=torch.float64, device=dev) if initial else None
+    rc = lib().chem_integrate_adjoint(mech.handle, ckpt.handle, _ptr(gT, "gT", shape=(n,)),
+                                      _ptr(gY, "gY", shape=(mech.K, n)), n, _ptr(g, "g_lnA"),
+                                      1 if per_cell else 0, _ptr(gT0, "gT0", allow_none=True),
+                                      _ptr(gY0, "gY0", allow_none=True), _stream())
+    _check(rc, "chem_integrate_adjoint")
+    return g, gT0, gY0
+
+
+class IntegrateFn(torch.autograd.Function):
+    """(T1, Y1) = integrate(T, P, Y; lnA) as a differentiable function of T, Y
+    and lnA.  The backward pass is the library's discrete adjoint over the
+    checkpointed accepted steps (step sizes frozen)."""
+
+    @staticmethod
+    def forward(ctx, T, P, Y, lnA, mech, dt, rtol=1e-6, atol=1e-10, opts=None):
+        T1, Y1, _, _, _, ck = integrate(mech, T.detach().contiguous(), P.detach().contiguous(),
+                                        Y.detach().contiguous(), dt, rtol, atol,
+                                        lnA=lnA.detach().contiguous(), opts=opts, checkpoint=True)
+        ctx.mech, ctx.ck, ctx.device = mech, ck, T.device
+        return T1, Y1
+
+    @staticmethod
+    def backward(ctx, gT, gY):
+        n = ctx.ck.n
+        dev = ctx.device
+        gT = torch.zeros(n, dtype=torch.float64, device=dev) if gT is None else gT.contiguous()
+        gY = torch.zeros((ctx.mech.K, n), dtype=torch.float64, device=dev) if gY is None else gY.contiguous()
+        g, gT0, gY0 = adjoint(ctx.mech, ctx.ck, gT, gY, per_cell=False, initial=True)
+        ctx.ck.close()
+        return gT0, None, gY0, g, None, None, None, None, None
+
+
+def autotune(mech, T, P, Y, dt, rtol=1e-6, atol=1e-10):
+    """Run the library's autotuner on this batch; returns (chosen Opts, list of
+    candidate times in ms)."""
+    import numpy as np
+    n = T.numel()
+    o = Opts()
+    ms = np.zeros(8)
+    rc = lib().chem_autotune(mech.handle, n, _ptr(T, "T", shape=(n,)), _ptr(P, "P", shape=(n,)),
+                             _ptr(Y, "Y", shape=(mech.K, n)), n, float(dt), float(rtol), float(atol),
+                             C.byref(o), ms.ctypes.data_as(C.c_void_p), _stream())
+    _check(rc, "chem_autotune")
+    return o, [float(x) for x in ms if x >= 0]
+
+
+class Graph:
+    """One split step captured in a HIP graph (chem_graph_create).  The tensors
+    given here are the ones every replay reads and writes."""
+
+    def __init__(self, mech, T, P, Y, dt, rtol=1e-6, atol=1e-10, out=None, h=None, n_steps=None,
+                 status=None, lnA=None, opts=None):
+        n, K = T.numel(), mech.K
+        self.mech = mech
+        self.T1, self.Y1 = out if out is not None else (torch.empty_like(T), torch.empty_like(Y))
+        self.h, self.n_steps, self.status = h, n_steps, status
+        self._keep = (T, P, Y, lnA)
+        o = opts if opts is not None else default_opts()
+        g = C.c_void_p()
+        rc = lib().chem_graph_create(mech.handle, n, _ptr(T, "T", shape=(n,)), _ptr(P, "P", shape=(n,)),
+                                     _ptr(Y, "Y", shape=(K, n)), n, _ptr(self.T1, "T_out", shape=(n,)),
+                                     _ptr(self.Y1, "Y_out", shape=(K, n)), float(dt), float(rtol),
+                                     float(atol), _ptr(h, "h", shape=(n,), allow_none=True),
+                                     _ptr(n_steps, "n_steps", torch.int32, (n,), allow_none=True),
+                                     _ptr(status, "status", torch.int32, (n,), allow_none=True),
+                                     _ptr(lnA, "lnA", shape=(mech.Nr,), allow_none=True), C.byref(o),
+                                     C.byref(g))
+        _check(rc, "chem_graph_create")
+        self.handle = g
+
+    def launch(self):
+        _check(lib().chem_graph_launch(self.handle, _stream()), "chem_graph_launch")
+        return self.T1, self.Y1
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().chem_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def evaluate(mech, phi, P, lnA=None, jacobian=True):

@@ -16,7 +16,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <map>
 #include <mutex>
 #include <new>
@@ -27,6 +31,7 @@
 #include "mech.h"
 #include "ros4.h"
 #include "team.h"
+#include "adjoint.h"
 
 namespace chem {
 
@@ -193,6 +198,11 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
     ck_rec = p.ck_off ? p.ck_off[c] : 0;
   };
   auto finish = [&](int64_t c) {
+    if (p.ck_data) {
+      double* rec = p.ck_data + (p.ck_off[c + 1] - 1) * (int64_t)(N + 1);
+      for (int i = 0; i < N; ++i) rec[i] = phi[i];
+      rec[N] = 0.0;
+    }
     double T;
     from_phi(M, P, phi, p.Y_out, p.ldY, c, &T);
     p.T_out[c] = T;
@@ -268,7 +278,8 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
         bad = 0;
         double fac = (err > 0.0) ? p.safety * pow(err, -0.25) : p.fac_max;
         if (err <= 1.0) {
-          if (p.ck_data) {
+          // (a record slot exists for every step the counting pass saw)
+          if (p.ck_data && ck_rec + accepted < p.ck_off[cell + 1] - 1) {
             double* rec = p.ck_data + (ck_rec + accepted) * (int64_t)(N + 1);
             for (int i = 0; i < N; ++i) rec[i] = phi[i];
             rec[N] = hs;
@@ -390,7 +401,8 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       bad = 0;
       double fac = (err > 0.0) ? p.safety * pow(err, -0.25) : p.fac_max;
       if (err <= 1.0) {
-        if (p.ck_data) {
+        // (a record slot exists for every step the counting pass saw)
+        if (p.ck_data && ck_rec + accepted < p.ck_off[cell + 1] - 1) {
           double* rec = p.ck_data + (ck_rec + accepted) * (int64_t)(N + 1);
           if (lane < N) rec[lane] = phi;
           if (lane == 0) rec[N] = hs;
@@ -408,6 +420,11 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
         last_rej = true;
         h = hs * fac;
       }
+    }
+    if (p.ck_data) {
+      double* rec = p.ck_data + (p.ck_off[cell + 1] - 1) * (int64_t)(N + 1);
+      if (lane < N) rec[lane] = phi;
+      if (lane == 0) rec[N] = 0.0;
     }
     // ---- output conversion: n_K from the ideal-gas closure, Y_k = n_k W_k / mass
     {
@@ -442,6 +459,175 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
   }
 }
 
+
+// ------------------------------------------------------------------ discrete adjoint, one wavefront per cell
+struct AdjParams {
+  MechView M;
+  int64_t n;
+  const double* ck_data;   // per cell: accepted (Phi_n, h_n) records, then the final state
+  const int64_t* ck_off;   // [n + 1]
+  const double* P;         // [n]
+  const double* T0;        // [n] initial state (copy)
+  const double* Y0;        // [K][n]
+  const double* gT;        // [n]
+  const double* gY;        // [K][ldY]
+  int64_t ldY;
+  const double* lnA;       // nullable, as in the forward call
+  double* g_cell;          // [Nr][n] per-cell d L / d ln A, file order
+  double* gT0;             // nullable [n]
+  double* gY0;             // nullable [K][ldY]
+};
+
+__global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
+  extern __shared__ double lds_raw[];
+  const MechView& M = a.M;
+  const int N = M.N, K = M.K, ldj = N + 1;
+  const int lane = threadIdx.x;
+  const size_t mat = (size_t)N * ldj;
+  double* vb = lds_raw + 2 * mat;
+  int* plane = (int*)(vb + 2 * TeamLdsT<double>::vec_elems(N));
+  double* pbar = vb + 2 * TeamLdsT<double>::vec_elems(N) + 32;   // [Nr] d L / d ln A of this cell
+  TeamLdsT<double> LA, LB;
+  TeamLdsT<Dd> LD;
+  LA.bind2(lds_raw, vb, plane, N);
+  LB.bind2(lds_raw + mat, vb, plane, N);
+  LD.bind2((Dd*)lds_raw, (Dd*)vb, plane, N);
+  const int64_t cell = blockIdx.x;
+  if (cell >= a.n) return;
+  const double P = a.P[cell];
+  const int64_t off = a.ck_off[cell];
+  const int64_t cnt = a.ck_off[cell + 1] - off - 1;
+
+  // ---- output conversion adjoint: L = gT T + sum_k gY_k Y_k,
+  //      Y_i = a_i / m, a_k = n_k W_k, a_b = n_b W_b, n_b = P V/(R T) - sum n_k
+  double lam;
+  {
+    const double* fin = a.ck_data + (off + cnt) * (int64_t)(N + 1);
+    const double phi = (lane < N) ? fin[lane] : 0.0;
+    const double T = bcast(phi, 0), V = bcast(phi, 1);
+    const double nk = gather(phi, lane + 2 < 64 ? lane + 2 : 0);
+    const double n_here = (lane < K - 1) ? nk : 0.0;
+    const double nb = P * V / (RU * T) - wave_sum(n_here);
+    const double ai = (lane < K - 1) ? n_here * M.W[lane] : (lane == K - 1 ? nb * M.W[K - 1] : 0.0);
+    const double mass = wave_sum(ai);
+    const double gy = (lane < K) ? a.gY[(int64_t)lane * a.ldY + cell] : 0.0;
+    const double sgy = wave_sum(gy * ai) / mass;
+    const double abar = (lane < K) ? (gy - sgy) / mass : 0.0;     // d L / d a_lane
+    const double abW = bcast(abar, K - 1) * M.W[K - 1];
+    const double abk = gather(abar, lane >= 2 ? lane - 2 : 0);
+    lam = 0.0;
+    if (lane == 0) lam = a.gT[cell] - abW * P * V / (RU * T * T);
+    if (lane == 1) lam = abW * P / (RU * T);
+    if (lane >= 2 && lane < N) lam = abk * M.W[lane - 2] - abW;
+  }
+  for (int j = lane; j < M.Nr; j += 64) pbar[j] = 0.0;
+  wsync();
+
+  for (int64_t s = cnt - 1; s >= 0; --s) {
+    const double* rec = a.ck_data + (off + s) * (int64_t)(N + 1);
+    const double x = (lane < N) ? rec[lane] : 0.0;
+    const double h = rec[N];
+    // ---- recompute the forward step
+    const double f1 = team_rhs_jac<double>(M, P, x, LA, a.lnA);
+    const double d = 1.0 / (h * ROS4_GAMMA);
+    if (lane < N)
+      for (int i = 0; i < N; ++i) LA.J[i * ldj + lane] = (i == lane ? d : 0.0) - LA.J[i * ldj + lane];
+    wsync();
+    int perm;
+    double rdiag;
+    team_lu(LA.J, ldj, N, perm, rdiag);
+    if (lane < N) plane[perm] = lane;
+    wsync();
+    const int invperm = (lane < N) ? plane[lane] : lane;
+    wsync();
+    const double ih = 1.0 / h;
+    const double* F = LA.J;
+    const double u1 = team_solve(F, ldj, N, perm, rdiag, f1);
+    const double y2 = x + ROS4_A21 * u1;
+    const double F2 = team_rhs(M, P, y2, LA, a.lnA);
+    const double u2 = team_solve(F, ldj, N, perm, rdiag, F2 + (ROS4_C21 * ih) * u1);
+    const double y3 = x + ROS4_A31 * u1 + ROS4_A32 * u2;
+    const double F3 = team_rhs(M, P, y3, LA, a.lnA);
+    const double u3 = team_solve(F, ldj, N, perm, rdiag, F3 + (ROS4_C31 * u1 + ROS4_C32 * u2) * ih);
+    const double u4 = team_solve(F, ldj, N, perm, rdiag,
+                                 F3 + (ROS4_C41 * u1 + ROS4_C42 * u2 + ROS4_C43 * u3) * ih);
+    // ---- reverse
+    double phib = lam;
+    double ub1 = ROS4_M1 * lam, ub2 = ROS4_M2 * lam, ub3 = ROS4_M3 * lam;
+    const double ub4 = ROS4_M4 * lam;
+    const double mu4 = team_solve_t(F, ldj, N, invperm, rdiag, ub4);
+    double F3b = mu4;
+    ub1 += ROS4_C41 * ih * mu4;
+    ub2 += ROS4_C42 * ih * mu4;
+    ub3 += ROS4_C43 * ih * mu4;
+    const double mu3 = team_solve_t(F, ldj, N, invperm, rdiag, ub3);
+    F3b += mu3;
+    ub1 += ROS4_C31 * ih * mu3;
+    ub2 += ROS4_C32 * ih * mu3;
+    team_rhs_jac<double>(M, P, y3, LB, a.lnA);
+    const double y3b = team_jt_mu(LB.J, ldj, N, F3b);
+    team_pbar<double>(M, P, y3, F3b, LB, a.lnA, pbar, true);
+    phib += y3b;
+    ub1 += ROS4_A31 * y3b;
+    ub2 += ROS4_A32 * y3b;
+    const double mu2 = team_solve_t(F, ldj, N, invperm, rdiag, ub2);
+    ub1 += ROS4_C21 * ih * mu2;
+    team_rhs_jac<double>(M, P, y2, LB, a.lnA);
+    const double y2b = team_jt_mu(LB.J, ldj, N, mu2);
+    team_pbar<double>(M, P, y2, mu2, LB, a.lnA, pbar, true);
+    phib += y2b;
+    ub1 += ROS4_A21 * y2b;
+    const double mu1 = team_solve_t(F, ldj, N, invperm, rdiag, ub1);
+    wsync();
+    // ---- J(Phi)^T mu1 and the terms through M(Phi): dual evaluations along u_i
+#pragma unroll 1
+    for (int i = 0; i < 4; ++i) {
+      const double ui = (i == 0) ? u1 : (i == 1) ? u2 : (i == 2) ? u3 : u4;
+      const double mui = (i == 0) ? mu1 : (i == 1) ? mu2 : (i == 2) ? mu3 : mu4;
+      team_rhs_jac<Dd>(M, P, Dd{x, (lane < N) ? ui : 0.0}, LD, a.lnA);
+      double vpart, dpart;
+      team_jt_mu_dual(LD.J, ldj, N, mui, vpart, dpart);
+      phib += dpart;
+      if (i == 0) phib += vpart;
+      team_pbar<Dd>(M, P, Dd{x, (lane < N) ? ui : 0.0}, mui, LD, a.lnA, pbar, i == 0);
+      wsync();
+    }
+    lam = (lane < N) ? phib : 0.0;
+  }
+
+  // ---- input conversion adjoint: Phi0 = (T0, R T0 S / P, Y_k / W_k), S = sum Y_k / W_k
+  if (a.gT0 || a.gY0) {
+    const double T0 = a.T0[cell];
+    const double yw = (lane < K) ? a.Y0[(int64_t)lane * a.n + cell] / M.W[lane] : 0.0;
+    const double S = wave_sum(yw);
+    const double lT = bcast(lam, 0), lV = bcast(lam, 1);
+    const double ln = gather(lam, lane + 2 < 64 ? lane + 2 : 0);
+    if (a.gT0 && lane == 0) a.gT0[cell] = lT + lV * RU * S / P;
+    if (a.gY0 && lane < K) {
+      double g = lV * RU * T0 / (P * M.W[lane]);
+      if (lane < K - 1) g += ln / M.W[lane];
+      a.gY0[(int64_t)lane * a.ldY + cell] = g;
+    }
+  }
+  for (int j = lane; j < M.Nr; j += 64) a.g_cell[(int64_t)M.rorig[j] * a.n + cell] = pbar[j];
+}
+
+// g[j] = sum over cells of g_cell[j][cell], in a fixed order (deterministic).
+__global__ void __launch_bounds__(256) reduce_cells_kernel(const double* __restrict__ g_cell, int64_t n,
+                                                           double* __restrict__ g) {
+  __shared__ double part[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int64_t c = threadIdx.x; c < n; c += 256) s += g_cell[(int64_t)j * n + c];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g[j] = part[0];
+}
+
 // f and J at given states, for tests of the pieces.
 __global__ void eval_kernel(MechView M, int64_t n, const double* __restrict__ phi_in, int64_t ldp,
                             const double* __restrict__ P, const double* __restrict__ lnA,
@@ -468,6 +654,19 @@ __global__ void eval_kernel(MechView M, int64_t n, const double* __restrict__ ph
 
 __global__ void reset_counter_kernel(unsigned int* q) { *q = 0u; }
 
+// Strided sample of a batch: cell i of the sample is cell i * stride.
+__global__ void sample_cells_kernel(int64_t ns, int64_t stride, int K, const double* __restrict__ T,
+                                    const double* __restrict__ P, const double* __restrict__ Y,
+                                    int64_t ldY, double* __restrict__ Ts, double* __restrict__ Ps,
+                                    double* __restrict__ Ys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const int64_t c = i * stride;
+  Ts[i] = T[c];
+  Ps[i] = P[c];
+  for (int k = 0; k < K; ++k) Ys[(int64_t)k * ns + i] = Y[(int64_t)k * ldY + c];
+}
+
 }  // namespace chem
 
 // ====================================================================== host side
@@ -488,20 +687,29 @@ struct chem_mech_s {
   int n_cu = 0;
   std::mutex mu;
   std::map<hipStream_t, Workspace> ws;
+  std::map<int, chem_opts> tuned;   // batch-size bucket -> autotuned options
+  bool cache_read = false;
+};
+
+struct chem_graph_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 struct chem_ckpt_s {
   chem_mech_t mech = nullptr;
   hipStream_t stream = nullptr;
-  int64_t n = 0, ldY = 0;
-  double* data = nullptr;        // records (Phi_n, h) for every accepted step
-  int64_t* off = nullptr;        // [n+1]
+  int64_t n = 0;
+  double* data = nullptr;        // per cell: (Phi_n, h_n) of every accepted step, then the final Phi
+  int64_t* off = nullptr;        // [n+1] record offsets
   double* P = nullptr;           // copy of the pressures [n]
   double* T0 = nullptr;          // copy of the initial state: T [n], Y [K][n]
   double* Y0 = nullptr;
-  double* lnA = nullptr;         // [Nr] the ln A used
-  int64_t total = 0;
-  double rtol = 0, atol = 0;
+  double* lnA = nullptr;         // [Nr] copy of the ln A override, or null
+  int64_t total = 0;             // records
+  std::vector<int64_t> off_host;
 };
 
 namespace {
@@ -549,6 +757,52 @@ int get_workspace(chem_mech_t m, hipStream_t s, int64_t slots, Workspace** out) 
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+int size_bucket(int64_t n) {
+  int b = 0;
+  while ((int64_t)1 << (b + 1) <= n) ++b;
+  return b;
+}
+
+std::string tune_key(chem_mech_t m, int bucket) {
+  std::ostringstream k;
+  k << "N" << m->view.N << " Nr" << m->view.Nr << " cu" << m->n_cu << " b" << bucket;
+  return k.str();
+}
+
+// Reads CHEM_AUTOTUNE_CACHE once per handle (lines: "<key> mode wg waves").
+void tune_cache_read(chem_mech_t m) {
+  if (m->cache_read) return;
+  m->cache_read = true;
+  const char* path = getenv("CHEM_AUTOTUNE_CACHE");
+  if (!path) return;
+  std::ifstream in(path);
+  std::string line;
+  const std::string pre = "N" + std::to_string(m->view.N) + " Nr" + std::to_string(m->view.Nr) +
+                          " cu" + std::to_string(m->n_cu) + " b";
+  while (std::getline(in, line)) {
+    if (line.compare(0, pre.size(), pre) != 0) continue;
+    std::istringstream is(line.substr(pre.size()));
+    int b, mode, wg, waves;
+    if (is >> b >> mode >> wg >> waves) {
+      chem_opts o;
+      chem_opts_default(&o);
+      o.mode = mode;
+      o.wg_size = wg;
+      o.waves_per_cu = waves;
+      m->tuned[b] = o;          // later lines win
+    }
+  }
+}
+
+bool tuned_lookup(chem_mech_t m, int64_t n, chem_opts* out) {
+  std::lock_guard<std::mutex> g(m->mu);
+  tune_cache_read(m);
+  auto it = m->tuned.find(size_bucket(n));
+  if (it == m->tuned.end()) return false;
+  *out = it->second;
+  return true;
+}
+
 typedef void (*TeamKernel)(IntParams, bool);
 
 // One wavefront per cell holds a state vector element per lane: N <= 64.
@@ -568,7 +822,7 @@ void chem_opts_default(chem_opts* o) {
   o->fac_max = 6.0;
   o->T_cut = 0.0;
   o->max_steps = 100000;
-  o->mode = CHEM_MODE_PLAIN;
+  o->mode = CHEM_MODE_AUTO;
   o->wg_size = 0;
   o->waves_per_cu = 0;
   o->stats = nullptr;
@@ -690,10 +944,98 @@ int chem_eval(chem_mech_t m, int64_t n, const double* phi, int64_t ld, const dou
   return CHEM_OK;
 }
 
+static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const double* P,
+                          const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
+                          double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
+                          const double* lnA, const chem_opts* opts, double* ck_data,
+                          const int64_t* ck_off, hipStream_t stream);
+
 int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P, const double* Y_in,
                    int64_t ldY, double* T_out, double* Y_out, double dt, double rtol, double atol,
                    double* h_io, int32_t* n_steps, int32_t* status, const double* lnA,
                    const chem_opts* opts, chem_ckpt_t* ckpt_out, hipStream_t stream) {
+  if (!ckpt_out)
+    return integrate_impl(m, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
+                          status, lnA, opts, nullptr, nullptr, stream);
+  *ckpt_out = nullptr;
+  if (!m || n <= 0 || !T_in || !P || !Y_in || !T_out || !Y_out || ldY < n) return CHEM_EINVAL;
+  HIPCHECK(hipSetDevice(m->device));
+  const int K = m->view.K, N = m->view.N;
+  // pass 1 counts the accepted steps of every cell (into scratch outputs, so
+  // that in-place calls keep their inputs); the integration is deterministic,
+  // so pass 2 repeats the same steps and records them
+  double *tT = nullptr, *tY = nullptr, *th = nullptr;
+  int32_t* tn = nullptr;
+  chem_ckpt_t c = new (std::nothrow) chem_ckpt_s();
+  if (!c) return CHEM_ENOMEM;
+  c->mech = m;
+  c->stream = stream;
+  c->n = n;
+  auto fail = [&](int rc) {
+    if (tT) (void)hipFree(tT);
+    if (tY) (void)hipFree(tY);
+    if (th) (void)hipFree(th);
+    if (tn) (void)hipFree(tn);
+    chem_ckpt_free(c);
+    return rc;
+  };
+  if (hipMalloc(&tT, n * 8) || hipMalloc(&tY, (size_t)K * n * 8) || hipMalloc(&th, n * 8) ||
+      hipMalloc(&tn, n * 4) || hipMalloc(&c->P, n * 8) || hipMalloc(&c->T0, n * 8) ||
+      hipMalloc(&c->Y0, (size_t)K * n * 8) || hipMalloc(&c->off, (n + 1) * 8))
+    return fail(CHEM_ENOMEM);
+  if (lnA) {
+    if (hipMalloc(&c->lnA, (size_t)m->view.Nr * 8)) return fail(CHEM_ENOMEM);
+    if (hipMemcpyAsync(c->lnA, lnA, (size_t)m->view.Nr * 8, hipMemcpyDeviceToDevice, stream)) return fail(CHEM_EHIP);
+  }
+  if (hipMemcpyAsync(c->P, P, n * 8, hipMemcpyDeviceToDevice, stream) ||
+      hipMemcpyAsync(c->T0, T_in, n * 8, hipMemcpyDeviceToDevice, stream) ||
+      hipMemcpy2DAsync(c->Y0, n * 8, Y_in, ldY * 8, n * 8, K, hipMemcpyDeviceToDevice, stream))
+    return fail(CHEM_EHIP);
+  if (h_io) {
+    if (hipMemcpyAsync(th, h_io, n * 8, hipMemcpyDeviceToDevice, stream)) return fail(CHEM_EHIP);
+  } else if (hipMemsetAsync(th, 0, n * 8, stream)) {
+    return fail(CHEM_EHIP);
+  }
+  int rc = integrate_impl(m, n, c->T0, c->P, c->Y0, n, tT, tY, dt, rtol, atol, th, tn, nullptr,
+                          c->lnA, opts, nullptr, nullptr, stream);
+  if (rc) return fail(rc);
+  std::vector<int32_t> steps(n);
+  if (hipMemcpyAsync(steps.data(), tn, n * 4, hipMemcpyDeviceToHost, stream) ||
+      hipStreamSynchronize(stream))
+    return fail(CHEM_EHIP);
+  c->off_host.resize(n + 1);
+  c->off_host[0] = 0;
+  for (int64_t i = 0; i < n; ++i) c->off_host[i + 1] = c->off_host[i] + steps[i] + 1;
+  c->total = c->off_host[n];
+  if (hipMalloc(&c->data, (size_t)c->total * (N + 1) * 8)) return fail(CHEM_ENOMEM);
+  if (hipMemcpyAsync(c->off, c->off_host.data(), (n + 1) * 8, hipMemcpyHostToDevice, stream))
+    return fail(CHEM_EHIP);
+  // pass 2: same inputs (the copies), the caller's outputs and h
+  double* h2 = th;
+  if (h_io) {
+    // restore the caller's initial h (pass 1 overwrote the scratch copy only)
+    h2 = h_io;
+  } else if (hipMemsetAsync(th, 0, n * 8, stream)) {
+    return fail(CHEM_EHIP);
+  }
+  rc = integrate_impl(m, n, c->T0, c->P, c->Y0, n, T_out, Y_out, dt, rtol, atol, h2, n_steps, status,
+                      c->lnA, opts, c->data, c->off, stream);
+  if (rc) return fail(rc);
+  if (hipStreamSynchronize(stream)) return fail(CHEM_EHIP);
+  (void)hipFree(tT);
+  (void)hipFree(tY);
+  (void)hipFree(th);
+  (void)hipFree(tn);
+  *ckpt_out = c;
+  return CHEM_OK;
+}
+
+static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const double* P,
+                          const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
+                          double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
+                          const double* lnA, const chem_opts* opts, double* ck_data,
+                          const int64_t* ck_off, hipStream_t stream) {
+
   if (!m || n < 0) return CHEM_EINVAL;
   if (n > 0 && (!T_in || !P || !Y_in || !T_out || !Y_out)) return CHEM_EINVAL;
   if (!(dt > 0) || !(rtol > 0) || !(atol >= 0) || ldY < n) return CHEM_EINVAL;
@@ -703,9 +1045,16 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   if (o.mode < CHEM_MODE_AUTO || o.mode > CHEM_MODE_TEAM_PERSISTENT) return CHEM_EINVAL;
   if (o.wg_size < 0 || o.wg_size > 256 || (o.wg_size % 64) != 0) return CHEM_EINVAL;
   if (o.max_steps <= 0 || !(o.fac_min > 0) || !(o.fac_max >= 1) || !(o.safety > 0)) return CHEM_EINVAL;
-  if (ckpt_out) *ckpt_out = nullptr;
   if (n == 0) return CHEM_OK;
   HIPCHECK(hipSetDevice(m->device));
+  if (o.mode == CHEM_MODE_AUTO) {
+    chem_opts t;
+    if (tuned_lookup(m, n, &t)) {
+      o.mode = t.mode;
+      o.wg_size = t.wg_size;
+      o.waves_per_cu = t.waves_per_cu;
+    }
+  }
   int mode = o.mode;
   if (mode == CHEM_MODE_AUTO) mode = (m->view.N <= 64) ? CHEM_MODE_TEAM_PERSISTENT : CHEM_MODE_PERSISTENT;
   // one wavefront per cell needs N <= 64; larger mechanisms use one cell per thread
@@ -742,6 +1091,8 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
     p.lnA = lnA;
     p.queue = w->queue;
     p.stats = o.stats;
+    p.ck_data = ck_data;
+    p.ck_off = ck_off;
     TeamKernel kern = team_kernel(m->view.N);
     const size_t lds = TeamLds::doubles(m->view.N) * sizeof(double);
     unsigned grid = (unsigned)n;
@@ -799,8 +1150,8 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   p.ld = slots;
   p.queue = w->queue;
   p.stats = o.stats;
-  p.ck_data = nullptr;
-  p.ck_off = nullptr;
+  p.ck_data = ck_data;
+  p.ck_off = ck_off;
   p.ck_count = nullptr;
   const unsigned grid = (unsigned)(slots / wg);
   if (persistent) {
@@ -810,18 +1161,215 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
     hipLaunchKernelGGL(integrate_thread_kernel<false>, dim3(grid), dim3(wg), 0, stream, p);
   }
   HIPCHECK(hipGetLastError());
-  (void)ckpt_out;
   return CHEM_OK;
 }
 
 int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, const double* gY,
                            int64_t ldY, double* g_lnA, int32_t per_cell, double* gT0, double* gY0,
                            hipStream_t stream) {
-  (void)m; (void)ckpt; (void)gT; (void)gY; (void)ldY; (void)g_lnA; (void)per_cell; (void)gT0;
-  (void)gY0; (void)stream;
-  return CHEM_EINVAL;
+  if (!m || !ckpt || ckpt->mech != m || !gT || !gY || !g_lnA || ldY < ckpt->n) return CHEM_EINVAL;
+  const int N = m->view.N, Nr = m->view.Nr;
+  const int64_t n = ckpt->n;
+  if (N > 64) return CHEM_EUNSUPPORTED;
+  const size_t lds = (2 * (size_t)N * (N + 1) + 2 * TeamLdsT<double>::vec_elems(N) + 32 + Nr) * 8;
+  if (lds > 65536) return CHEM_EUNSUPPORTED;
+  HIPCHECK(hipSetDevice(m->device));
+  double* g_cell = per_cell ? g_lnA : nullptr;
+  if (!per_cell && hipMalloc(&g_cell, (size_t)Nr * n * 8)) return CHEM_ENOMEM;
+  AdjParams a;
+  a.M = m->view;
+  a.n = n;
+  a.ck_data = ckpt->data;
+  a.ck_off = ckpt->off;
+  a.P = ckpt->P;
+  a.T0 = ckpt->T0;
+  a.Y0 = ckpt->Y0;
+  a.gT = gT;
+  a.gY = gY;
+  a.ldY = ldY;
+  a.lnA = ckpt->lnA;
+  a.g_cell = g_cell;
+  a.gT0 = gT0;
+  a.gY0 = gY0;
+  hipLaunchKernelGGL(adjoint_team_kernel, dim3((unsigned)n), dim3(64), lds, stream, a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && !per_cell) {
+    hipLaunchKernelGGL(reduce_cells_kernel, dim3(Nr), dim3(256), 0, stream, g_cell, n, g_lnA);
+    e = hipGetLastError();
+  }
+  if (!per_cell) {
+    // the reduction must finish before the scratch is released
+    if (hipStreamSynchronize(stream) != hipSuccess) e = hipErrorUnknown;
+    (void)hipFree(g_cell);
+  }
+  return e == hipSuccess ? CHEM_OK : CHEM_EHIP;
 }
 
-void chem_ckpt_free(chem_ckpt_t c) { delete c; }
+int chem_ckpt_export(chem_ckpt_t c, int64_t* off, double* records) {
+  if (!c) return CHEM_EINVAL;
+  if (off)
+    for (int64_t i = 0; i <= c->n; ++i) off[i] = c->off_host[i];
+  if (records) {
+    const int N = c->mech->view.N;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return CHEM_EHIP;
+    if (hipMemcpy(records, c->data, (size_t)c->total * (N + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return CHEM_EHIP;
+  }
+  return CHEM_OK;
+}
+
+int64_t chem_ckpt_records(chem_ckpt_t c) { return c ? c->total : -1; }
+
+int chem_autotune(chem_mech_t m, int64_t n, const double* T_in, const double* P, const double* Y_in,
+                  int64_t ldY, double dt, double rtol, double atol, chem_opts* chosen, double* ms,
+                  hipStream_t stream) {
+  if (!m || n <= 0 || !T_in || !P || !Y_in || ldY < n) return CHEM_EINVAL;
+  HIPCHECK(hipSetDevice(m->device));
+  const int K = m->view.K, N = m->view.N;
+  const int64_t ns = std::min<int64_t>(n, 4096);
+  const int64_t stride = n / ns;
+  double *Ts = nullptr, *Ps = nullptr, *Ys = nullptr, *To = nullptr, *Yo = nullptr;
+  auto cleanup = [&]() {
+    for (double* q : {Ts, Ps, Ys, To, Yo})
+      if (q) (void)hipFree(q);
+  };
+  if (hipMalloc(&Ts, ns * 8) || hipMalloc(&Ps, ns * 8) || hipMalloc(&Ys, (size_t)K * ns * 8) ||
+      hipMalloc(&To, ns * 8) || hipMalloc(&Yo, (size_t)K * ns * 8)) {
+    cleanup();
+    return CHEM_ENOMEM;
+  }
+  hipLaunchKernelGGL(sample_cells_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, stream, ns,
+                     stride, K, T_in, P, Y_in, ldY, Ts, Ps, Ys);
+  std::vector<chem_opts> cand;
+  auto add = [&](int mode, int wg, int waves) {
+    chem_opts o;
+    chem_opts_default(&o);
+    o.mode = mode;
+    o.wg_size = wg;
+    o.waves_per_cu = waves;
+    cand.push_back(o);
+  };
+  if (N <= 64) {
+    add(CHEM_MODE_TEAM, 0, 0);
+    for (int w : {0, 2, 3, 4}) add(CHEM_MODE_TEAM_PERSISTENT, 0, w);
+  }
+  if (N <= 16 || N > 64) {
+    add(CHEM_MODE_PLAIN, 64, 0);
+    add(CHEM_MODE_PLAIN, 256, 0);
+    add(CHEM_MODE_PERSISTENT, 64, 0);
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) || hipEventCreate(&e1)) {
+    cleanup();
+    return CHEM_EHIP;
+  }
+  double best = 1e300;
+  int best_i = -1;
+  int rc = CHEM_OK;
+  for (size_t i = 0; i < cand.size() && rc == CHEM_OK; ++i) {
+    double t_best = 1e300;
+    for (int rep = 0; rep < 3 && rc == CHEM_OK; ++rep) {
+      (void)hipEventRecord(e0, stream);
+      rc = integrate_impl(m, ns, Ts, Ps, Ys, ns, To, Yo, dt, rtol, atol, nullptr, nullptr, nullptr,
+                          nullptr, &cand[i], nullptr, nullptr, stream);
+      (void)hipEventRecord(e1, stream);
+      float t = 0;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+        rc = CHEM_EHIP;
+      if (rep > 0) t_best = std::min(t_best, (double)t);   // the first run warms up
+    }
+    if (ms && i < 8) ms[i] = t_best;
+    if (t_best < best) {
+      best = t_best;
+      best_i = (int)i;
+    }
+  }
+  if (ms)
+    for (size_t i = cand.size(); i < 8; ++i) ms[i] = -1.0;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  cleanup();
+  if (rc) return rc;
+  const int bucket = size_bucket(n);
+  {
+    std::lock_guard<std::mutex> g(m->mu);
+    tune_cache_read(m);
+    m->tuned[bucket] = cand[best_i];
+  }
+  if (const char* path = getenv("CHEM_AUTOTUNE_CACHE")) {
+    std::ofstream out(path, std::ios::app);
+    out << tune_key(m, bucket) << " " << cand[best_i].mode << " " << cand[best_i].wg_size << " "
+        << cand[best_i].waves_per_cu << "\n";
+  }
+  if (chosen) *chosen = cand[best_i];
+  return CHEM_OK;
+}
+
+int chem_graph_create(chem_mech_t m, int64_t n, const double* T_in, const double* P, const double* Y_in,
+                      int64_t ldY, double* T_out, double* Y_out, double dt, double rtol, double atol,
+                      double* h_io, int32_t* n_steps, int32_t* status, const double* lnA,
+                      const chem_opts* opts, chem_graph_t* out) {
+  if (!m || !out || n <= 0) return CHEM_EINVAL;
+  *out = nullptr;
+  HIPCHECK(hipSetDevice(m->device));
+  chem_graph_t g = new (std::nothrow) chem_graph_s();
+  if (!g) return CHEM_ENOMEM;
+  g->device = m->device;
+  if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return CHEM_EHIP;
+  }
+  // relaxed capture: a first call may allocate the stream's workspace (that
+  // allocation runs immediately and is not part of the graph)
+  if (hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    chem_graph_free(g);
+    return CHEM_EHIP;
+  }
+  const int rc = integrate_impl(m, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
+                                status, lnA, opts, nullptr, nullptr, g->stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(g->stream, &graph);
+  if (rc || e != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    chem_graph_free(g);
+    return rc ? rc : CHEM_EHIP;
+  }
+  g->graph = graph;
+  if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    chem_graph_free(g);
+    return CHEM_EHIP;
+  }
+  *out = g;
+  return CHEM_OK;
+}
+
+int chem_graph_launch(chem_graph_t g, hipStream_t stream) {
+  if (!g || !g->exec) return CHEM_EINVAL;
+  HIPCHECK(hipSetDevice(g->device));
+  HIPCHECK(hipGraphLaunch(g->exec, stream));
+  return CHEM_OK;
+}
+
+void chem_graph_free(chem_graph_t g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+}
+
+void chem_ckpt_free(chem_ckpt_t c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->data) (void)hipFree(c->data);
+  if (c->off) (void)hipFree(c->off);
+  if (c->P) (void)hipFree(c->P);
+  if (c->T0) (void)hipFree(c->T0);
+  if (c->Y0) (void)hipFree(c->Y0);
+  if (c->lnA) (void)hipFree(c->lnA);
+  delete c;
+}
 
 }  // extern "C"

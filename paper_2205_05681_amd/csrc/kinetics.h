@@ -28,11 +28,55 @@
 
 namespace chem {
 
-struct Lane {
-  double* __restrict__ p;
+template <class S>
+struct LaneT {
+  S* __restrict__ p;
   int64_t ld;
-  __device__ __forceinline__ double& operator[](int i) const { return p[(int64_t)i * ld]; }
+  __device__ __forceinline__ S& operator[](int i) const { return p[(int64_t)i * ld]; }
 };
+using Lane = LaneT<double>;
+
+using ::exp;
+using ::log;
+using ::log10;
+
+// Forward-mode dual number: value and derivative along one direction.  Used
+// for directional derivatives of the Jacobian in the adjoint sweep.
+struct Dd {
+  double v, d;
+};
+__device__ __forceinline__ Dd dd(double v, double d = 0.0) { return Dd{v, d}; }
+__device__ __forceinline__ Dd operator+(Dd a, Dd b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dd operator-(Dd a, Dd b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dd operator-(Dd a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dd operator*(Dd a, Dd b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dd operator/(Dd a, Dd b) {
+  const double q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Dd operator+(Dd a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ Dd operator+(double b, Dd a) { return {a.v + b, a.d}; }
+__device__ __forceinline__ Dd operator-(Dd a, double b) { return {a.v - b, a.d}; }
+__device__ __forceinline__ Dd operator-(double b, Dd a) { return {b - a.v, -a.d}; }
+__device__ __forceinline__ Dd operator*(Dd a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dd operator*(double b, Dd a) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dd operator/(Dd a, double b) { return {a.v / b, a.d / b}; }
+__device__ __forceinline__ Dd operator/(double b, Dd a) {
+  const double q = b / a.v;
+  return {q, -q * a.d / a.v};
+}
+__device__ __forceinline__ Dd& operator+=(Dd& a, Dd b) { a = a + b; return a; }
+__device__ __forceinline__ Dd& operator-=(Dd& a, Dd b) { a = a - b; return a; }
+__device__ __forceinline__ Dd& operator*=(Dd& a, Dd b) { a = a * b; return a; }
+__device__ __forceinline__ Dd& operator+=(Dd& a, double b) { a.v += b; return a; }
+__device__ __forceinline__ Dd exp(Dd a) { const double e = exp(a.v); return {e, e * a.d}; }
+__device__ __forceinline__ Dd log(Dd a) { return {log(a.v), a.d / a.v}; }
+__device__ __forceinline__ Dd log10(Dd a) { return {log10(a.v), a.d / (a.v * 2.302585092994045684)}; }
+__device__ __forceinline__ double val(double x) { return x; }
+__device__ __forceinline__ double val(Dd x) { return x.v; }
+template <class S> __device__ __forceinline__ S sc(double x);
+template <> __device__ __forceinline__ double sc<double>(double x) { return x; }
+template <> __device__ __forceinline__ Dd sc<Dd>(double x) { return Dd{x, 0.0}; }
 
 // Workspace rows of one slot (in units of ld).  N = K + 1.
 struct WsLayout {
@@ -82,21 +126,24 @@ __device__ __forceinline__ double thermo(const MechView& M, double T, Lane hrt, 
 }
 
 // Rate data of one reaction at (T, C).
-struct RateOut {
-  double q;        // rate of progress
-  double kf_rf;    // k * prod C^nu'
-  double kr_rr;    // k_r * prod C^nu''
-  double kf;       // effective forward rate constant
-  double kr;       // reverse rate constant
-  double dlnk_dT;  // d ln k / dT at fixed C
-  double dlnKc_dT; // d ln K_c / dT
-  double beta;     // d q / d[M] (0 for elementary reactions)
+template <class S>
+struct RateOutT {
+  S q;        // rate of progress
+  S kf_rf;    // k * prod C^nu'
+  S kr_rr;    // k_r * prod C^nu''
+  S kf;       // effective forward rate constant
+  S kr;       // reverse rate constant
+  S dlnk_dT;  // d ln k / dT at fixed C
+  S dlnKc_dT; // d ln K_c / dT
+  S beta;     // d q / d[M] (0 for elementary reactions)
 };
+using RateOut = RateOutT<double>;
 
-__device__ __forceinline__ RateOut reaction_rate(const MechView& M, int j, double T, double lnT,
-                                                 double iT, double ctot, Lane conc, Lane gib,
-                                                 Lane hrt, const double* __restrict__ lnA_over,
-                                                 bool want_deriv) {
+template <class S>
+__device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S T, S lnT, S iT,
+                                                     S ctot, LaneT<S> conc, LaneT<S> gib,
+                                                     LaneT<S> hrt, const double* __restrict__ lnA_over,
+                                                     bool want_deriv) {
   const int32_t* info = M.rinfo + 8 * j;
   const int32_t* sp = M.rspec + 6 * j;
   const int32_t* nu = M.rnu + 6 * j;
@@ -104,62 +151,63 @@ __device__ __forceinline__ RateOut reaction_rate(const MechView& M, int j, doubl
   const int type = info[0], nr = info[1], np = info[2];
   const double lnA = lnA_over ? lnA_over[M.rorig[j]] : ar[0];
   const double b = ar[1], th = ar[2], dnu = ar[3];
-  const double lnkinf = lnA + b * lnT - th * iT;
-  const double kinf = exp(lnkinf);
-  const double dlnkinf = (b + th * iT) * iT;
-  double k = kinf, dlnk = dlnkinf, dk_dM = 0.0;
+  const S lnkinf = lnA + b * lnT - th * iT;
+  const S kinf = exp(lnkinf);
+  const S dlnkinf = (b + th * iT) * iT;
+  S k = kinf, dlnk = dlnkinf, dk_dM = sc<S>(0.0);
   if (type != RX_ELEM) {
-    double Mc = ctot;
+    S Mc = ctot;
     for (int e = info[3]; e < info[4]; ++e) Mc += M.eff_am1[e] * conc[M.eff_idx[e]];
     if (type == RX_THIRD) {
       k = kinf * Mc;
       dk_dM = kinf;
     } else {
       const double* f = M.fo + 8 * info[5];
-      const double lnk0 = lnA + f[0] + f[1] * lnT - f[2] * iT;
-      const double k0 = exp(lnk0);
-      const double dlnk0 = (f[1] + f[2] * iT) * iT;
-      const double Pr = k0 * Mc / kinf;
-      double F = 1.0, dlnF_dlnPr = 0.0, dlnF_dT_fc = 0.0;
+      const S lnk0 = lnA + f[0] + f[1] * lnT - f[2] * iT;
+      const S k0 = exp(lnk0);
+      const S dlnk0 = (f[1] + f[2] * iT) * iT;
+      const S Pr = k0 * Mc / kinf;
+      S F = sc<S>(1.0), dlnF_dlnPr = sc<S>(0.0), dlnF_dT_fc = sc<S>(0.0);
       if (type == RX_TROE) {
         const double a = f[3], T3 = f[4], T1 = f[5], T2 = f[6];
-        const double e3 = exp(-T * (1.0 / T3)), e1 = exp(-T * (1.0 / T1));
-        const double e2 = T2 > 0.0 ? exp(-T2 * iT) : 0.0;
-        const double Fc = (1.0 - a) * e3 + a * e1 + e2;
-        const double lFc = log10(Fc);
-        const double c = -0.4 - 0.67 * lFc, n = 0.75 - 1.27 * lFc;
-        const bool tiny = !(Pr > 1e-300);
-        const double lPr = tiny ? -300.0 : log10(Pr);
-        const double x = lPr + c, den = n - 0.14 * x, y = x / den;
-        const double opy = 1.0 + y * y;
-        const double L = lFc / opy;
+        const S e3 = exp(-T * (1.0 / T3)), e1 = exp(-T * (1.0 / T1));
+        const S e2 = T2 > 0.0 ? exp(-T2 * iT) : sc<S>(0.0);
+        const S Fc = (1.0 - a) * e3 + a * e1 + e2;
+        const S lFc = log10(Fc);
+        const S c = -0.4 - 0.67 * lFc, n = 0.75 - 1.27 * lFc;
+        const bool tiny = !(val(Pr) > 1e-300);
+        const S lPr = tiny ? sc<S>(-300.0) : log10(Pr);
+        const S x = lPr + c, den = n - 0.14 * x, y = x / den;
+        const S opy = 1.0 + y * y;
+        const S L = lFc / opy;
         F = exp(L * 2.302585092994045684);
         if (want_deriv) {
-          const double dLdy = -2.0 * lFc * y / (opy * opy);
-          const double dydx = n / (den * den), dydn = -x / (den * den);
-          dlnF_dlnPr = tiny ? 0.0 : dLdy * dydx;
-          const double dLdlFc = 1.0 / opy + dLdy * (dydx * -0.67 + dydn * -1.27);
-          const double dFc = -(1.0 - a) * (1.0 / T3) * e3 - a * (1.0 / T1) * e1 + (T2 > 0.0 ? T2 * iT * iT * e2 : 0.0);
+          const S dLdy = -2.0 * lFc * y / (opy * opy);
+          const S dydx = n / (den * den), dydn = -x / (den * den);
+          dlnF_dlnPr = tiny ? sc<S>(0.0) : dLdy * dydx;
+          const S dLdlFc = 1.0 / opy + dLdy * (dydx * -0.67 + dydn * -1.27);
+          const S dFc = -(1.0 - a) * (1.0 / T3) * e3 - a * (1.0 / T1) * e1 +
+                        (T2 > 0.0 ? T2 * iT * iT * e2 : sc<S>(0.0));
           dlnF_dT_fc = dLdlFc * dFc / Fc;
         }
       }
-      const double pfac = Pr / (1.0 + Pr);
+      const S pfac = Pr / (1.0 + Pr);
       k = kinf * pfac * F;
       if (want_deriv) {
-        const double phi = 1.0 / (1.0 + Pr) + dlnF_dlnPr;   // d ln k / d ln Pr
+        const S phi = 1.0 / (1.0 + Pr) + dlnF_dlnPr;   // d ln k / d ln Pr
         dk_dM = k * phi / Mc;
         dlnk = dlnkinf + phi * (dlnk0 - dlnkinf) + dlnF_dT_fc;
       }
     }
   }
-  double sg = 0.0, sh = 0.0;
-  double rf = 1.0, rr = 1.0;
+  S sg = sc<S>(0.0), sh = sc<S>(0.0);
+  S rf = sc<S>(1.0), rr = sc<S>(1.0);
   for (int i = 0; i < nr; ++i) {
     const int s = sp[i];
     const double v = nu[i];
     sg -= v * gib[s];
     if (want_deriv) sh -= v * hrt[s];
-    const double cs = conc[s];
+    const S cs = conc[s];
     rf *= (nu[i] == 1) ? cs : (nu[i] == 2 ? cs * cs : cs * cs * cs);
   }
   for (int i = 0; i < np; ++i) {
@@ -167,12 +215,12 @@ __device__ __forceinline__ RateOut reaction_rate(const MechView& M, int j, doubl
     const double v = nu[3 + i];
     sg += v * gib[s];
     if (want_deriv) sh += v * hrt[s];
-    const double cs = conc[s];
+    const S cs = conc[s];
     rr *= (nu[3 + i] == 1) ? cs : (nu[3 + i] == 2 ? cs * cs : cs * cs * cs);
   }
-  const double lnKc = sg + dnu * log(PATM / (RU * T));
-  const double kr = k * exp(-lnKc);
-  RateOut o;
+  const S lnKc = sg + dnu * log(PATM / (RU * T));
+  const S kr = k * exp(-lnKc);
+  RateOutT<S> o;
   o.kf = k;
   o.kr = kr;
   o.kf_rf = k * rf;

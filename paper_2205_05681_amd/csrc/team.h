@@ -57,6 +57,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
 }
 
+__device__ __forceinline__ Dd wave_sum(Dd v) { return Dd{wave_sum(v.v), wave_sum(v.d)}; }
+__device__ __forceinline__ Dd bcast(Dd v, int src) { return Dd{bcast(v.v, src), bcast(v.d, src)}; }
+
+// LDS accumulation (FP64 LDS atomics); a dual number adds both components.
+__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
+__device__ __forceinline__ void lds_add(Dd* p, Dd v) {
+  atomicAdd(&p->v, v.v);
+  atomicAdd(&p->d, v.d);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp<DPP_QUAD_1032>(v));
   v = fmax(v, dpp<DPP_QUAD_2301>(v));
@@ -65,31 +75,32 @@ __device__ __forceinline__ double wave_max(double v) {
   return fmax(fmax(bcast(v, 0), bcast(v, 16)), fmax(bcast(v, 32), bcast(v, 48)));
 }
 
-// Per-wavefront LDS scratch.  ldj = N + 1 (odd row stride in doubles).
-struct TeamLds {
-  double* J;      // [N][ldj]   Jacobian being assembled / kept for re-factorisation
-  double* brow;   // [ldj]      bath-gas row of d wdot / d Phi
-  double* conc;   // [64]
-  double* hrt;    // [64]
-  double* cpr;    // [64]
-  double* gib;    // [64]
-  double* wdot;   // [64]
-  double* gb;     // [64]      G column of the bath gas
-  double* tb;     // [64]      uniform third-body part per row
-  double* dwdT;   // [64]
-  double* dwdV;   // [64]
-  double* vec;    // [64]      staging of a lane-distributed vector
-  double* prow;   // [2][64]   pivot-row broadcast (double buffered)
-  int* plane;     // [64]      lane holding the k-th pivot row
+// Per-wavefront LDS scratch.  ldj = N + 1 (odd row stride).
+template <class S>
+struct TeamLdsT {
+  S* J;      // [N][ldj]   Jacobian being assembled / factors of M
+  S* brow;   // [ldj]      bath-gas row of d wdot / d Phi
+  S* conc;   // [64]
+  S* hrt;    // [64]
+  S* cpr;    // [64]
+  S* gib;    // [64]
+  S* wdot;   // [64]
+  S* gb;     // [64]       G column of the bath gas
+  S* tb;     // [64]       uniform third-body part per row
+  S* dwdT;   // [64]
+  S* dwdV;   // [64]
+  S* vec;    // [64]       staging of a lane-distributed vector
+  int* plane;            // [64]
+  // elements of S after the matrix: brow and the vectors
+  static __host__ __device__ size_t vec_elems(int N) { return (size_t)(N + 1) + 10 * 64; }
   static __host__ __device__ size_t doubles(int N) {
-    const int ldj = N + 1;
-    return (size_t)N * ldj + ldj + 11 * 64 + 128 + 32;
+    return ((size_t)N * (N + 1) + vec_elems(N)) * (sizeof(S) / sizeof(double)) + 32;
   }
-  __device__ void bind(double* base, int N) {
-    const int ldj = N + 1;
-    J = base;
-    brow = J + (size_t)N * ldj;
-    conc = brow + ldj;
+  // matrix at Jb, vectors at Vb (separately placed for the adjoint's two views)
+  __device__ void bind2(S* Jb, S* Vb, int* pl, int N) {
+    J = Jb;
+    brow = Vb;
+    conc = brow + (N + 1);
     hrt = conc + 64;
     cpr = hrt + 64;
     gib = cpr + 64;
@@ -99,10 +110,14 @@ struct TeamLds {
     dwdT = tb + 64;
     dwdV = dwdT + 64;
     vec = dwdV + 64;
-    prow = vec + 64;
-    plane = (int*)(prow + 128);
+    plane = pl;
+  }
+  __device__ void bind(double* base, int N) {
+    S* b = (S*)base;
+    bind2(b, b + (size_t)N * (N + 1), (int*)(base + doubles(N) - 32), N);
   }
 };
+using TeamLds = TeamLdsT<double>;
 
 // Lane-distributed LDS view with a fixed stride, to reuse reaction_rate().
 struct LdsLane {
@@ -113,31 +128,32 @@ struct LdsLane {
 // Concentrations and thermo of the state y (lane-distributed, element i in
 // lane i).  Returns (T, V, sum C) uniform; fills conc/hrt/cpr/gib in LDS.
 // sdcp (optional) receives sum_k C_k dcp_k/dT / R.
-__device__ __forceinline__ void team_state(const MechView& M, double P, double y, TeamLds& L,
-                                           double& T, double& V, double& ctot, double* sdcp) {
+template <class S>
+__device__ __forceinline__ void team_state(const MechView& M, double P, S y, TeamLdsT<S>& L, S& T,
+                                           S& V, S& ctot, S* sdcp) {
   const int lane = threadIdx.x;
   const int K = M.K;
   T = bcast(y, 0);
   V = bcast(y, 1);
   L.vec[lane] = y;
   wsync();
-  double c = 0.0;
+  S c = sc<S>(0.0);
   if (lane < K - 1) c = L.vec[lane + 2] / V;
-  const double s = wave_sum(c);
+  const S s = wave_sum(c);
   if (lane == K - 1) c = P / (RU * T) - s;
   ctot = wave_sum(c);
   if (lane < K) L.conc[lane] = c;
-  double dcp = 0.0;
+  S dcp = sc<S>(0.0);
   if (lane < K) {
     const double* cf = M.nasa + 15 * lane;
-    const bool lo = T < cf[0];
+    const bool lo = val(T) < cf[0];
     const double a0 = lo ? cf[1] : cf[8], a1 = lo ? cf[2] : cf[9], a2 = lo ? cf[3] : cf[10],
                  a3 = lo ? cf[4] : cf[11], a4 = lo ? cf[5] : cf[12], a5 = lo ? cf[6] : cf[13],
                  a6 = lo ? cf[7] : cf[14];
-    const double lnT = log(T), iT = 1.0 / T;
-    const double cp = a0 + T * (a1 + T * (a2 + T * (a3 + T * a4)));
-    const double h = a0 + T * (a1 * 0.5 + T * (a2 * (1.0 / 3.0) + T * (a3 * 0.25 + T * a4 * 0.2))) + a5 * iT;
-    const double sr = a0 * lnT + T * (a1 + T * (a2 * 0.5 + T * (a3 * (1.0 / 3.0) + T * a4 * 0.25))) + a6;
+    const S lnT = log(T), iT = 1.0 / T;
+    const S cp = a0 + T * (a1 + T * (a2 + T * (a3 + T * a4)));
+    const S h = a0 + T * (a1 * 0.5 + T * (a2 * (1.0 / 3.0) + T * (a3 * 0.25 + T * a4 * 0.2))) + a5 * iT;
+    const S sr = a0 * lnT + T * (a1 + T * (a2 * 0.5 + T * (a3 * (1.0 / 3.0) + T * a4 * 0.25))) + a6;
     L.hrt[lane] = h;
     L.cpr[lane] = cp;
     L.gib[lane] = sr - h;
@@ -153,7 +169,7 @@ __device__ double team_rhs(const MechView& M, double P, double y, TeamLds& L,
   const int lane = threadIdx.x;
   const int K = M.K, N = M.N;
   double T, V, ctot;
-  team_state(M, P, y, L, T, V, ctot, nullptr);
+  team_state<double>(M, P, y, L, T, V, ctot, nullptr);
   if (lane < K) L.wdot[lane] = 0.0;
   wsync();
   const double lnT = log(T), iT = 1.0 / T;
@@ -186,77 +202,79 @@ __device__ double team_rhs(const MechView& M, double P, double y, TeamLds& L,
   return f;
 }
 
-// f(y) and the Jacobian, assembled in L.J (row i at L.J[i*(N+1)]).
-__device__ double team_rhs_jac(const MechView& M, double P, double y, TeamLds& L,
-                               const double* __restrict__ lnA) {
+// f(y) and the Jacobian, assembled in L.J (row i at L.J[i*(N+1)]).  S is
+// double, or the dual type for a directional derivative of f and J.
+template <class S>
+__device__ S team_rhs_jac(const MechView& M, double P, S y, TeamLdsT<S>& L,
+                          const double* __restrict__ lnA) {
   const int lane = threadIdx.x;
   const int K = M.K, N = M.N, ldj = N + 1;
-  double T, V, ctot, sdcp;
+  S T, V, ctot, sdcp;
   team_state(M, P, y, L, T, V, ctot, &sdcp);
-  const double lnT = log(T), iT = 1.0 / T, iV = 1.0 / V;
+  const S lnT = log(T), iT = 1.0 / T, iV = 1.0 / V;
   // clear: column `lane` of every species row, the bath row and the per-row sums
   if (lane < N) {
-    for (int k = 0; k < K - 1; ++k) L.J[(k + 2) * ldj + lane] = 0.0;
-    L.brow[lane] = 0.0;
+    for (int k = 0; k < K - 1; ++k) L.J[(k + 2) * ldj + lane] = sc<S>(0.0);
+    L.brow[lane] = sc<S>(0.0);
   }
   if (lane < K) {
-    L.wdot[lane] = 0.0;
-    L.gb[lane] = 0.0;
-    L.tb[lane] = 0.0;
+    L.wdot[lane] = sc<S>(0.0);
+    L.gb[lane] = sc<S>(0.0);
+    L.tb[lane] = sc<S>(0.0);
   }
   wsync();
   for (int j = lane; j < M.Nr; j += 64) {
-    const RateOut r = reaction_rate(M, j, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
-                                    Lane{L.hrt, 1}, lnA, true);
+    const RateOutT<S> r = reaction_rate(M, j, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
+                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, lnA, true);
     const int32_t* info = M.rinfo + 8 * j;
     const int32_t* sp = M.rspec + 6 * j;
     const int32_t* nu = M.rnu + 6 * j;
     const int nr = info[1], np = info[2];
-    const double dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
-    double dq[6];
+    const S dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
+    S dq[6];
     int ms[6];
     int nm = 0;
     for (int i = 0; i < nr; ++i) {
-      double d = r.kf;
+      S d = r.kf;
       for (int l = 0; l < nr; ++l) {
-        const double c = L.conc[sp[l]];
+        const S c = L.conc[sp[l]];
         const int v = (l == i) ? nu[l] - 1 : nu[l];
         if (v >= 1) d *= c;
         if (v >= 2) d *= c;
         if (v >= 3) d *= c;
       }
       ms[nm] = sp[i];
-      dq[nm++] = d * nu[i];
+      dq[nm++] = d * (double)nu[i];
     }
     for (int i = 0; i < np; ++i) {
-      double d = r.kr;
+      S d = r.kr;
       for (int l = 0; l < np; ++l) {
-        const double c = L.conc[sp[3 + l]];
+        const S c = L.conc[sp[3 + l]];
         const int v = (l == i) ? nu[3 + l] - 1 : nu[3 + l];
         if (v >= 1) d *= c;
         if (v >= 2) d *= c;
         if (v >= 3) d *= c;
       }
       ms[nm] = sp[3 + i];
-      dq[nm++] = -d * nu[3 + i];
+      dq[nm++] = d * (double)-nu[3 + i];
     }
     for (int side = 0; side < 2; ++side) {
       const int cnt = side ? np : nr;
       for (int i = 0; i < cnt; ++i) {
         const int k = sp[3 * side + i];
         const double vk = side ? (double)nu[3 + i] : -(double)nu[i];
-        double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-        atomicAdd(&L.wdot[k], vk * r.q);
-        atomicAdd(&row[0], vk * dqdT);
+        S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+        lds_add(&L.wdot[k], vk * r.q);
+        lds_add(&row[0], vk * dqdT);
         for (int t = 0; t < nm; ++t) {
           const int m = ms[t];
-          atomicAdd((m == K - 1) ? &L.gb[k] : &row[m + 2], vk * dq[t]);
+          lds_add((m == K - 1) ? &L.gb[k] : &row[m + 2], vk * dq[t]);
         }
         if (info[0] != RX_ELEM) {
-          atomicAdd(&L.tb[k], vk * r.beta);
+          lds_add(&L.tb[k], vk * r.beta);
           for (int e = info[3]; e < info[4]; ++e) {
             const int m = M.eff_idx[e];
-            atomicAdd((m == K - 1) ? &L.gb[k] : &row[m + 2], vk * M.eff_am1[e] * r.beta);
+            lds_add((m == K - 1) ? &L.gb[k] : &row[m + 2], (vk * M.eff_am1[e]) * r.beta);
           }
         }
       }
@@ -264,26 +282,26 @@ __device__ double team_rhs_jac(const MechView& M, double P, double y, TeamLds& L
   }
   wsync();
   // pass 1, row-parallel (lane k = species row): Phi coordinates of row k
-  const double dCb_dT = -P / (RU * T * T);
-  double num = 0.0, den = 0.0, wsum = 0.0, wcp = 0.0, dDV = 0.0;
+  const S dCb_dT = -P / (RU * T * T);
+  S num = sc<S>(0.0), den = sc<S>(0.0), wsum = sc<S>(0.0), wcp = sc<S>(0.0), dDV = sc<S>(0.0);
   if (lane < K) {
     const int k = lane;
-    double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-    const double t = L.tb[k];
-    const double gbk = L.gb[k] + t;
-    const double wk = L.wdot[k];
-    const double cpk = L.cpr[k] * RU;
+    S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+    const S t = L.tb[k];
+    const S gbk = L.gb[k] + t;
+    const S wk = L.wdot[k];
+    const S cpk = L.cpr[k] * RU;
     num = L.hrt[k] * RU * T * wk;
     den = L.conc[k] * cpk;
     wsum = wk;
     wcp = wk * cpk;
-    double dvs = 0.0;
+    S dvs = sc<S>(0.0);
     for (int m = 0; m < K - 1; ++m) {
-      const double dn = row[m + 2] + t - gbk;
+      const S dn = row[m + 2] + t - gbk;
       dvs -= dn * L.conc[m];
       row[m + 2] = dn;
     }
-    const double dwdT = row[0] + gbk * dCb_dT;
+    const S dwdT = row[0] + gbk * dCb_dT;
     L.dwdT[k] = dwdT;
     L.dwdV[k] = dvs * iV;
     if (k < K - 1) {
@@ -299,28 +317,28 @@ __device__ double team_rhs_jac(const MechView& M, double P, double y, TeamLds& L
   dDV = wave_sum(dDV) * iV;
   wsync();
   // pass 2, column-parallel (lane c = column): the T and V rows
-  const double Tdot = -num / den;
-  const double RTP = RU * T / P;
+  const S Tdot = -num / den;
+  const S RTP = RU * T / P;
   if (lane < N) {
     const int c = lane;
-    double ah = 0.0, aw = 0.0;
+    S ah = sc<S>(0.0), aw = sc<S>(0.0);
     if (c >= 2) {
       for (int k = 0; k < K; ++k) {
-        const double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-        const double d = row[c] * iV;           // d wdot_k / d n_m
+        const S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+        const S d = row[c] * iV;           // d wdot_k / d n_m
         ah += L.hrt[k] * RU * T * d;
         aw += d;
       }
     } else {
-      const double* src = (c == 0) ? L.dwdT : L.dwdV;
+      const S* src = (c == 0) ? L.dwdT : L.dwdV;
       for (int k = 0; k < K; ++k) {
-        const double d = src[k];
+        const S d = src[k];
         ah += L.hrt[k] * RU * T * d;
         aw += d;
       }
     }
-    const double cpb = L.cpr[K - 1] * RU;
-    double dD, dTd, dVd;
+    const S cpb = L.cpr[K - 1] * RU;
+    S dD, dTd, dVd;
     if (c == 0) {
       dD = sdcp * RU + cpb * dCb_dT;
       dTd = -(ah + wcp) / den - Tdot * dD / den;
@@ -337,7 +355,7 @@ __device__ double team_rhs_jac(const MechView& M, double P, double y, TeamLds& L
     L.J[c] = dTd;
     L.J[ldj + c] = dVd;
   }
-  double f = 0.0;
+  S f = sc<S>(0.0);
   if (lane == 0) f = Tdot;
   if (lane == 1) f = V * (Tdot * iT + RTP * wsum);
   if (lane >= 2 && lane < N) f = V * L.wdot[lane - 2];
