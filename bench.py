@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--mode", default="auto", help="headline launch mode")
     ap.add_argument("--compare", default="team,plain,persistent",
                     help="other modes to time (thread-per-cell modes take one step)")
+    ap.add_argument("--order", default="hot", choices=["hot", "index"],
+                    help="dispatch order of the cells: hottest first (library default) or index order")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -115,10 +117,12 @@ def main():
     ns = torch.empty(n, dtype=torch.int32, device=dev)
     st = torch.empty(n, dtype=torch.int32, device=dev)
 
+    order = {"hot": 1, "index": 0}[a.order]
+
     def step(mode):
         h.zero_()
-        chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=chem.default_opts(mode=mode), out=(T1, Y1),
-                       n_steps=ns, status=st)
+        chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=chem.default_opts(mode=mode, order=order),
+                       out=(T1, Y1), n_steps=ns, status=st)
 
     if a.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -133,7 +137,7 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-    opts = chem.default_opts(mode=a.mode)
+    opts = chem.default_opts(mode=a.mode, order=order)
     t0 = time.perf_counter()
     for i in range(a.steps):
         h.zero_()
@@ -151,7 +155,7 @@ def main():
     # ---- step statistics of the same call (deterministic), for the op count
     stats = torch.zeros(3, dtype=torch.int64, device=dev)
     h.zero_()
-    chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=chem.default_opts(mode=a.mode, stats=stats), out=(T1, Y1))
+    chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=chem.default_opts(mode=a.mode, order=order, stats=stats), out=(T1, Y1))
     torch.cuda.synchronize()
     attempts, accepted, rejected = (int(x) for x in stats.cpu().numpy())
     flops, trans = opcount.batch_flops(m, attempts, accepted)
@@ -201,7 +205,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "cells": n, "species": m.n_species, "reactions": len(m.reactions),
-                   "dt": dt, "rtol": 1e-6, "atol": 1e-10, "mode": a.mode,
+                   "dt": dt, "rtol": 1e-6, "atol": 1e-10, "mode": a.mode, "order": a.order,
                    "failed_cells": int((status != 0).sum()),
                    "accepted_steps_mean": round(float(steps_acc.mean()), 3),
                    "accepted_steps_max": int(steps_acc.max())},

@@ -60,6 +60,15 @@ extern "C" {
 #define CHEM_MODE_TEAM 3        /* one wavefront per cell (J and LU in registers/LDS) */
 #define CHEM_MODE_TEAM_PERSISTENT 4 /* one wavefront per cell, resident grid, work queue */
 
+/* ---- dispatch order (chem_opts.order) ---------------------------------- */
+#define CHEM_ORDER_INDEX 0      /* cells are taken in index order */
+#define CHEM_ORDER_HOT_FIRST 1  /* hottest cells first (T_in in 12 K buckets, descending): the
+                                   step count grows steeply with temperature, so the longest
+                                   cells start first and the tail of the launch is bounded by
+                                   the longest cell rather than by its position in the batch;
+                                   cells of similar cost also share a wavefront in the
+                                   one-cell-per-thread modes.  Results do not depend on it. */
+
 typedef struct chem_mech_s* chem_mech_t; /* opaque, library-owned */
 typedef struct chem_graph_s* chem_graph_t; /* opaque, library-owned captured split step */
 typedef struct chem_ckpt_s* chem_ckpt_t; /* opaque, library-owned adjoint checkpoint */
@@ -76,6 +85,7 @@ typedef struct {
   int32_t mode;           /* CHEM_MODE_* (CHEM_MODE_AUTO) */
   int32_t wg_size;        /* work-group size in threads (0 = library choice) */
   int32_t waves_per_cu;   /* persistent modes: resident waves per CU (0 = occupancy limit) */
+  int32_t order;          /* dispatch order of the cells: CHEM_ORDER_* (CHEM_ORDER_HOT_FIRST) */
   unsigned long long* stats; /* nullable DEVICE pointer to 3 counters that the call adds to:
                                 attempted steps, accepted steps, rejected steps (all cells) */
 } chem_opts;

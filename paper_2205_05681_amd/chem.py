@@ -32,7 +32,8 @@ class Opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("h_min", C.c_double),
                 ("safety", C.c_double), ("fac_min", C.c_double), ("fac_max", C.c_double),
                 ("T_cut", C.c_double), ("max_steps", C.c_int32), ("mode", C.c_int32),
-                ("wg_size", C.c_int32), ("waves_per_cu", C.c_int32), ("stats", C.c_void_p)]
+                ("wg_size", C.c_int32), ("waves_per_cu", C.c_int32), ("order", C.c_int32),
+                ("stats", C.c_void_p)]
 
 
 _vp = C.c_void_p

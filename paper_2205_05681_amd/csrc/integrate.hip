@@ -54,6 +54,8 @@ struct IntParams {
   int32_t* piv;
   int64_t ld;
   unsigned int* queue;
+  const int32_t* order;        // nullable: queue position -> cell
+  double* jsave;               // nullable: per work-group copy of J, [grid][N][64]
   unsigned long long* stats;   // nullable: attempts, accepted, rejected
   // adjoint checkpoint (nullable): per cell, accepted (Phi_n, h) records
   double* ck_data;          // [rec][N+1] per record, cell-major blocks
@@ -171,12 +173,9 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
   Lane conc{base + L.conc() * ld, ld}, wdot{base + L.wdot() * ld, ld};
   Lane hrt{base + L.hrt() * ld, ld}, cpr{base + L.cpr() * ld, ld}, gib{base + L.gibbs() * ld, ld};
 
-  int64_t cell;
-  if (PERSISTENT)
-    cell = atomicAdd(p.queue, 1u);
-  else
-    cell = slot;
-  bool have = cell < p.n;
+  int64_t q = PERSISTENT ? (int64_t)atomicAdd(p.queue, 1u) : slot;   // queue position
+  bool have = q < p.n;
+  int64_t cell = have ? (p.order ? p.order[q] : q) : 0;
   // per-cell controller state
   double P = 0, h = 0, rem = 0;
   int attempts = 0, accepted = 0, bad = 0, status = 0;
@@ -302,9 +301,12 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
     if (done) {
       finish(cell);
       if (PERSISTENT) {
-        cell = atomicAdd(p.queue, 1u);
-        have = cell < p.n;
-        if (have) init(cell);
+        q = atomicAdd(p.queue, 1u);
+        have = q < p.n;
+        if (have) {
+          cell = p.order ? p.order[q] : q;
+          init(cell);
+        }
       } else {
         have = false;
       }
@@ -314,6 +316,7 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
 
 
 // ------------------------------------------------------------------ one-wavefront-per-cell integrator
+template <int NMAX>
 __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PERSISTENT) {
   extern __shared__ double lds_raw[];
   const MechView& M = p.M;
@@ -321,15 +324,17 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
   const int lane = threadIdx.x;
   TeamLds L;
   L.bind(lds_raw, N);
-  int64_t cell;
+  double* const jsv = p.jsave ? p.jsave + (int64_t)blockIdx.x * N * 64 : nullptr;
+  int64_t q;   // queue position
   if (PERSISTENT) {
     unsigned c0 = 0;
     if (lane == 0) c0 = atomicAdd(p.queue, 1u);
-    cell = __shfl((int)c0, 0, 64);
+    q = (unsigned)__shfl((int)c0, 0, 64);
   } else {
-    cell = blockIdx.x;
+    q = blockIdx.x;
   }
-  while (cell < p.n) {
+  while (q < p.n) {
+    const int64_t cell = p.order ? p.order[q] : q;
     // ---- input conversion (eq. (conc_form1)), element i of Phi in lane i
     const double P = p.P[cell];
     const double T0 = p.T_in[cell];
@@ -344,7 +349,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
     double rem = p.dt, h = p.dt;
     if (p.h_io && p.h_io[cell] > 0.0) h = p.h_io[cell];
     int attempts = 0, accepted = 0, bad = 0, status = 0;
-    bool last_rej = false, need_jac = true;
+    bool last_rej = false, need_jac = true;   // need_jac: Phi changed since J was evaluated
     bool done = (p.T_cut > 0.0) && !(T0 >= p.T_cut);
     const int64_t ck_rec = p.ck_off ? p.ck_off[cell] : 0;
     double f1 = 0.0;
@@ -359,19 +364,24 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       }
       ++attempts;
       const double hs = fmin(h, rem);
-      if (need_jac) {
+      // J(Phi) into LDS: evaluated after an accepted step; after a rejection
+      // (same Phi, the LU has overwritten J) reloaded from this work-group's
+      // saved copy, or evaluated again where there is none
+      if (need_jac || !jsv) {
         f1 = team_rhs_jac(M, P, phi, L, p.lnA);
         need_jac = false;
+        if (jsv && lane < N)
+          for (int i = 0; i < N; ++i) jsv[i * 64 + lane] = L.J[i * ldj + lane];
+      } else {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");   // own stores done, L1 invalidated
+        if (lane < N)
+          for (int i = 0; i < N; ++i) L.J[i * ldj + lane] = jsv[i * 64 + lane];
+        wsync();
       }
-      // M = I/(h gamma) - J in place of J (J is re-evaluated after a rejection)
-      const double d = 1.0 / (hs * ROS4_GAMMA);
-      if (lane < N)
-        for (int i = 0; i < N; ++i) L.J[i * ldj + lane] = (i == lane ? d : 0.0) - L.J[i * ldj + lane];
-      need_jac = true;
-      wsync();
+      // factors of M = I/(h gamma) - J over J
       int perm;
       double rdiag;
-      const int rc = team_lu(L.J, ldj, N, perm, rdiag);
+      const int rc = team_lu<NMAX>(L.J, ldj, N, 1.0 / (hs * ROS4_GAMMA), perm, rdiag, L);
       double err = 0.0, ynew = 0.0;
       if (rc == 0) {
         const double ih = 1.0 / hs;
@@ -408,6 +418,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
           if (lane == 0) rec[N] = hs;
         }
         phi = ynew;
+        need_jac = true;
         rem -= hs;
         ++accepted;
         fac = fmin(p.fac_max, fmax(p.fac_min, fac));
@@ -452,7 +463,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
     if (PERSISTENT) {
       unsigned c1 = 0;
       if (lane == 0) c1 = atomicAdd(p.queue, 1u);
-      cell = __shfl((int)c1, 0, 64);
+      q = (unsigned)__shfl((int)c1, 0, 64);
     } else {
       break;
     }
@@ -478,6 +489,7 @@ struct AdjParams {
   double* gY0;             // nullable [K][ldY]
 };
 
+template <int NMAX>
 __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
   extern __shared__ double lds_raw[];
   const MechView& M = a.M;
@@ -529,13 +541,9 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
     const double h = rec[N];
     // ---- recompute the forward step
     const double f1 = team_rhs_jac<double>(M, P, x, LA, a.lnA);
-    const double d = 1.0 / (h * ROS4_GAMMA);
-    if (lane < N)
-      for (int i = 0; i < N; ++i) LA.J[i * ldj + lane] = (i == lane ? d : 0.0) - LA.J[i * ldj + lane];
-    wsync();
     int perm;
     double rdiag;
-    team_lu(LA.J, ldj, N, perm, rdiag);
+    team_lu<NMAX>(LA.J, ldj, N, 1.0 / (h * ROS4_GAMMA), perm, rdiag, LA);
     if (lane < N) plane[perm] = lane;
     wsync();
     const int invperm = (lane < N) ? plane[lane] : lane;
@@ -654,6 +662,66 @@ __global__ void eval_kernel(MechView M, int64_t n, const double* __restrict__ ph
 
 __global__ void reset_counter_kernel(unsigned int* q) { *q = 0u; }
 
+// ---- dispatch order: counting sort of the cells by a temperature bucket,
+// hottest first.  bins[0..255] counts, bins[256..511] cursors.  The order
+// inside a bucket depends on atomics; no result depends on it.
+constexpr int ORDER_BINS = 256;
+__device__ __forceinline__ int order_bucket(double T) {
+  if (!(T >= 0.0)) return 0;
+  if (T >= 12.0 * (ORDER_BINS - 1)) return ORDER_BINS - 1;
+  return (int)(T * (1.0 / 12.0));
+}
+
+__global__ void __launch_bounds__(ORDER_BINS) order_clear_kernel(unsigned int* bins) {
+  bins[threadIdx.x] = 0u;
+  bins[ORDER_BINS + threadIdx.x] = 0u;
+}
+
+__global__ void __launch_bounds__(256) order_count_kernel(int64_t n, const double* __restrict__ T,
+                                                          unsigned int* bins) {
+  __shared__ unsigned int c[ORDER_BINS];
+  c[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&c[order_bucket(T[i])], 1u);
+  __syncthreads();
+  if (c[threadIdx.x]) atomicAdd(&bins[threadIdx.x], c[threadIdx.x]);
+}
+
+// cursor[b] = number of cells in hotter buckets (one block of ORDER_BINS threads)
+__global__ void __launch_bounds__(ORDER_BINS) order_scan_kernel(unsigned int* bins) {
+  __shared__ unsigned int s[ORDER_BINS];
+  const int t = threadIdx.x;
+  s[t] = bins[ORDER_BINS - 1 - t];          // s[t]: count of the t-th hottest bucket
+  __syncthreads();
+  for (int d = 1; d < ORDER_BINS; d <<= 1) {
+    const unsigned int v = (t >= d) ? s[t - d] : 0u;
+    __syncthreads();
+    s[t] += v;
+    __syncthreads();
+  }
+  // exclusive prefix of the t-th hottest bucket
+  bins[ORDER_BINS + (ORDER_BINS - 1 - t)] = s[t] - bins[ORDER_BINS - 1 - t];
+}
+
+__global__ void __launch_bounds__(256) order_scatter_kernel(int64_t n, const double* __restrict__ T,
+                                                            unsigned int* bins, int32_t* __restrict__ order) {
+  __shared__ unsigned int c[ORDER_BINS], base[ORDER_BINS];
+  c[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  unsigned int r = 0u;
+  if (i < n) {
+    b = order_bucket(T[i]);
+    r = atomicAdd(&c[b], 1u);
+  }
+  __syncthreads();
+  if (c[threadIdx.x]) base[threadIdx.x] = atomicAdd(&bins[ORDER_BINS + threadIdx.x], c[threadIdx.x]);
+  __syncthreads();
+  if (i < n) order[base[b] + r] = (int32_t)i;
+}
+
 // Strided sample of a batch: cell i of the sample is cell i * stride.
 __global__ void sample_cells_kernel(int64_t ns, int64_t stride, int K, const double* __restrict__ T,
                                     const double* __restrict__ P, const double* __restrict__ Y,
@@ -675,8 +743,10 @@ using namespace chem;
 struct Workspace {
   double* ws = nullptr;
   int32_t* piv = nullptr;
-  unsigned int* queue = nullptr;
-  size_t ws_bytes = 0, piv_bytes = 0;
+  unsigned int* queue = nullptr;   // [0] work-queue counter, [64..575] dispatch-order bins
+  int32_t* order = nullptr;        // queue position -> cell
+  double* jsave = nullptr;         // persistent one-wavefront-per-cell mode: J copy per work-group
+  size_t ws_bytes = 0, piv_bytes = 0, order_bytes = 0, jsave_bytes = 0;
 };
 
 struct chem_mech_s {
@@ -735,12 +805,14 @@ int grow(void** p, size_t* have, size_t need) {
   return CHEM_OK;
 }
 
+constexpr size_t QUEUE_BYTES = (64 + 2 * ORDER_BINS) * sizeof(unsigned int);
+
 int get_workspace(chem_mech_t m, hipStream_t s, int64_t slots, Workspace** out) {
   std::lock_guard<std::mutex> g(m->mu);
   Workspace& w = m->ws[s];
   const WsLayout L{m->view.N, m->view.K};
   if (slots == 0) {
-    if (!w.queue && hipMalloc(&w.queue, 256) != hipSuccess) return CHEM_ENOMEM;
+    if (!w.queue && hipMalloc(&w.queue, QUEUE_BYTES) != hipSuccess) return CHEM_ENOMEM;
     *out = &w;
     return CHEM_OK;
   }
@@ -749,7 +821,7 @@ int get_workspace(chem_mech_t m, hipStream_t s, int64_t slots, Workspace** out) 
   rc = grow((void**)&w.piv, &w.piv_bytes, (size_t)m->view.N * slots * sizeof(int32_t));
   if (rc) return rc;
   if (!w.queue) {
-    if (hipMalloc(&w.queue, 256) != hipSuccess) return CHEM_ENOMEM;
+    if (hipMalloc(&w.queue, QUEUE_BYTES) != hipSuccess) return CHEM_ENOMEM;
   }
   *out = &w;
   return CHEM_OK;
@@ -806,7 +878,14 @@ bool tuned_lookup(chem_mech_t m, int64_t n, chem_opts* out) {
 typedef void (*TeamKernel)(IntParams, bool);
 
 // One wavefront per cell holds a state vector element per lane: N <= 64.
-TeamKernel team_kernel(int N) { return N <= 64 ? integrate_team_kernel : nullptr; }
+TeamKernel team_kernel(int N) {
+  if (N <= 16) return integrate_team_kernel<16>;
+  if (N <= 32) return integrate_team_kernel<32>;
+  if (N <= 48) return integrate_team_kernel<48>;
+  if (N <= 56) return integrate_team_kernel<56>;
+  if (N <= 64) return integrate_team_kernel<64>;
+  return nullptr;
+}
 
 }  // namespace
 
@@ -825,6 +904,7 @@ void chem_opts_default(chem_opts* o) {
   o->mode = CHEM_MODE_AUTO;
   o->wg_size = 0;
   o->waves_per_cu = 0;
+  o->order = CHEM_ORDER_HOT_FIRST;
   o->stats = nullptr;
 }
 
@@ -923,6 +1003,8 @@ void chem_mech_free(chem_mech_t m) {
     if (kv.second.ws) (void)hipFree(kv.second.ws);
     if (kv.second.piv) (void)hipFree(kv.second.piv);
     if (kv.second.queue) (void)hipFree(kv.second.queue);
+    if (kv.second.order) (void)hipFree(kv.second.order);
+    if (kv.second.jsave) (void)hipFree(kv.second.jsave);
   }
   if (m->blob) (void)hipFree(m->blob);
   delete m;
@@ -1030,13 +1112,35 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   return CHEM_OK;
 }
 
+// Dispatch order of the cells (hottest first) into w->order; *order receives
+// it, or null when the cells go in index order.  Four small kernels, no memset.
+static int build_order(chem_mech_t m, Workspace* w, int64_t n, const double* T_in, int32_t mode,
+                       hipStream_t stream, const int32_t** order) {
+  *order = nullptr;
+  if (mode != CHEM_ORDER_HOT_FIRST || n < 1024) return CHEM_OK;
+  {
+    std::lock_guard<std::mutex> g(m->mu);
+    const int rc = grow((void**)&w->order, &w->order_bytes, (size_t)n * sizeof(int32_t));
+    if (rc) return rc;
+  }
+  unsigned int* bins = w->queue + 64;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(order_clear_kernel, dim3(1), dim3(ORDER_BINS), 0, stream, bins);
+  hipLaunchKernelGGL(order_count_kernel, dim3(blocks), dim3(256), 0, stream, n, T_in, bins);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(ORDER_BINS), 0, stream, bins);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, n, T_in, bins, w->order);
+  HIPCHECK(hipGetLastError());
+  *order = w->order;
+  return CHEM_OK;
+}
+
 static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const double* P,
                           const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
                           double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
                           const double* lnA, const chem_opts* opts, double* ck_data,
                           const int64_t* ck_off, hipStream_t stream) {
 
-  if (!m || n < 0) return CHEM_EINVAL;
+  if (!m || n < 0 || n > INT32_MAX) return CHEM_EINVAL;
   if (n > 0 && (!T_in || !P || !Y_in || !T_out || !Y_out)) return CHEM_EINVAL;
   if (!(dt > 0) || !(rtol > 0) || !(atol >= 0) || ldY < n) return CHEM_EINVAL;
   chem_opts o;
@@ -1045,6 +1149,7 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
   if (o.mode < CHEM_MODE_AUTO || o.mode > CHEM_MODE_TEAM_PERSISTENT) return CHEM_EINVAL;
   if (o.wg_size < 0 || o.wg_size > 256 || (o.wg_size % 64) != 0) return CHEM_EINVAL;
   if (o.max_steps <= 0 || !(o.fac_min > 0) || !(o.fac_max >= 1) || !(o.safety > 0)) return CHEM_EINVAL;
+  if (o.order != CHEM_ORDER_INDEX && o.order != CHEM_ORDER_HOT_FIRST) return CHEM_EINVAL;
   if (n == 0) return CHEM_OK;
   HIPCHECK(hipSetDevice(m->device));
   if (o.mode == CHEM_MODE_AUTO) {
@@ -1066,8 +1171,12 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
     Workspace* w;
     int rc = get_workspace(m, stream, 0, &w);
     if (rc) return rc;
+    const int32_t* order;
+    rc = build_order(m, w, n, T_in, o.order, stream, &order);
+    if (rc) return rc;
     IntParams p;
     memset(&p, 0, sizeof(p));
+    p.order = order;
     p.M = m->view;
     p.n = n;
     p.T_in = T_in;
@@ -1102,6 +1211,12 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
       if (o.waves_per_cu > 0) per_cu = std::min(per_cu, o.waves_per_cu);
       if (per_cu < 1) per_cu = 1;
       grid = (unsigned)std::min<int64_t>((int64_t)m->n_cu * per_cu, n);
+      {
+        std::lock_guard<std::mutex> g(m->mu);
+        rc = grow((void**)&w->jsave, &w->jsave_bytes, (size_t)grid * m->view.N * 64 * sizeof(double));
+        if (rc) return rc;
+      }
+      p.jsave = w->jsave;
       hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, w->queue);
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, stream, p, persistent);
@@ -1123,7 +1238,12 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
   Workspace* w;
   int rc = get_workspace(m, stream, slots, &w);
   if (rc) return rc;
+  const int32_t* order;
+  rc = build_order(m, w, n, T_in, o.order, stream, &order);
+  if (rc) return rc;
   IntParams p;
+  memset(&p, 0, sizeof(p));
+  p.order = order;
   p.M = m->view;
   p.n = n;
   p.T_in = T_in;
@@ -1191,7 +1311,12 @@ int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, co
   a.g_cell = g_cell;
   a.gT0 = gT0;
   a.gY0 = gY0;
-  hipLaunchKernelGGL(adjoint_team_kernel, dim3((unsigned)n), dim3(64), lds, stream, a);
+  void (*kern)(AdjParams) = N <= 16   ? adjoint_team_kernel<16>
+                            : N <= 32 ? adjoint_team_kernel<32>
+                            : N <= 48 ? adjoint_team_kernel<48>
+                            : N <= 56 ? adjoint_team_kernel<56>
+                                      : adjoint_team_kernel<64>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)n), dim3(64), lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && !per_cell) {
     hipLaunchKernelGGL(reduce_cells_kernel, dim3(Nr), dim3(256), 0, stream, g_cell, n, g_lnA);

@@ -1,16 +1,17 @@
 // One wavefront per cell ("team" kernels).
 //
-// Layout inside a wavefront (64 lanes, N = K + 1 <= NMAX <= 64):
+// Layout inside a wavefront (64 lanes, N = K + 1 <= 64):
 //   * element i of every state-sized vector (Phi, f, u_1..u_4, ...) lives in
 //     lane i, one register each;
-//   * row i of the iteration matrix M = I/(h gamma) - J lives in lane i as
-//     NMAX registers; the LU runs with implicit partial pivoting (rows stay in
-//     their lanes, the pivot order is recorded), the pivot search is a wave
-//     max-reduction plus a ballot, the pivot row is broadcast through LDS;
 //   * reactions are spread over lanes (reaction j on lane j mod 64); their
 //     contributions to the production rates and to the Jacobian are scattered
 //     into LDS with FP64 LDS atomics, then the chain rule through C(Phi) is
 //     applied in one row-parallel and one column-parallel pass;
+//   * the LU of M = I/(h gamma) - J loads row i into lane i's registers and
+//     eliminates with implicit partial pivoting (rows stay in their lanes, the
+//     pivot order is recorded; the pivot search is a wave max-reduction plus
+//     a ballot, the pivot row is broadcast through LDS); the factors go back
+//     to LDS in pivot order for the triangular solves;
 //   * every controller decision is uniform over the wavefront.
 // Work-groups are one wavefront, so a work-group barrier is a wave barrier.
 #pragma once
@@ -35,10 +36,13 @@ __device__ __forceinline__ double bcast(double v, int src) {
 __device__ __forceinline__ double gather(double v, int src) { return __shfl(v, src, 64); }
 
 // Cross-lane move inside 16-lane rows (DPP); CTRL is the DPP control word.
+// The controls used here permute lanes inside a row, so every lane has a
+// source and the "old" operand (the value itself) is never taken.
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int l = __double2loint(v), h = __double2hiint(v);
+  const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(h, h, CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 constexpr int DPP_QUAD_1032 = 0xB1;   // quad_perm [1,0,3,2]
@@ -90,7 +94,13 @@ struct TeamLdsT {
   S* dwdT;   // [64]
   S* dwdV;   // [64]
   S* vec;    // [64]       staging of a lane-distributed vector
+  S* prow;   // [2][64]    LU pivot-row broadcast; aliases dwdT and dwdV, which
+             //            only the Jacobian assembly uses
   int* plane;            // [64]
+  // Two layouts.  bind(): dwdT and dwdV first, at the start of the work-group's
+  // LDS, so that the LU's pivot-row buffer has a compile-time address; then the
+  // matrix, brow and the other vectors.  bind2(): the matrix at Jb and every
+  // vector at Vb (the adjoint's two matrix views share one vector block).
   // elements of S after the matrix: brow and the vectors
   static __host__ __device__ size_t vec_elems(int N) { return (size_t)(N + 1) + 10 * 64; }
   static __host__ __device__ size_t doubles(int N) {
@@ -110,11 +120,25 @@ struct TeamLdsT {
     dwdT = tb + 64;
     dwdV = dwdT + 64;
     vec = dwdV + 64;
+    prow = dwdT;
     plane = pl;
   }
   __device__ void bind(double* base, int N) {
     S* b = (S*)base;
-    bind2(b, b + (size_t)N * (N + 1), (int*)(base + doubles(N) - 32), N);
+    dwdT = b;
+    dwdV = b + 64;
+    prow = dwdT;
+    J = b + 128;
+    brow = J + (size_t)N * (N + 1);
+    conc = brow + (N + 1);
+    hrt = conc + 64;
+    cpr = hrt + 64;
+    gib = cpr + 64;
+    wdot = gib + 64;
+    gb = wdot + 64;
+    tb = gb + 64;
+    vec = tb + 64;
+    plane = (int*)(base + doubles(N) - 32);
   }
 };
 using TeamLds = TeamLdsT<double>;
@@ -164,7 +188,7 @@ __device__ __forceinline__ void team_state(const MechView& M, double P, S y, Tea
 }
 
 // f(y) for lane-distributed y; returns f_i in lane i.
-__device__ double team_rhs(const MechView& M, double P, double y, TeamLds& L,
+__device__ __forceinline__ double team_rhs(const MechView& M, double P, double y, TeamLds& L,
                            const double* __restrict__ lnA) {
   const int lane = threadIdx.x;
   const int K = M.K, N = M.N;
@@ -205,7 +229,7 @@ __device__ double team_rhs(const MechView& M, double P, double y, TeamLds& L,
 // f(y) and the Jacobian, assembled in L.J (row i at L.J[i*(N+1)]).  S is
 // double, or the dual type for a directional derivative of f and J.
 template <class S>
-__device__ S team_rhs_jac(const MechView& M, double P, S y, TeamLdsT<S>& L,
+__device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, TeamLdsT<S>& L,
                           const double* __restrict__ lnA) {
   const int lane = threadIdx.x;
   const int K = M.K, N = M.N, ldj = N + 1;
@@ -363,68 +387,89 @@ __device__ S team_rhs_jac(const MechView& M, double P, S y, TeamLdsT<S>& L,
   return f;
 }
 
-// In-place LU with partial pivoting of the N x N matrix held in LDS (row i at
-// F[i * ldj]); rows are swapped explicitly so that, as in a textbook LU, the
-// pivot of column k is the largest |F[i][k]|, i >= k, ties to the lowest row.
-// The multipliers of column k are computed by lanes over rows and reach the
-// trailing update (lanes over columns) through v_readlane, so the update loop
-// only reads and writes its own column, eight rows at a time.
-// perm (lane-distributed) receives the row permutation: row i of the factors
-// is original row perm[i]; rdiag (lane-distributed) receives 1 / U_ii.
-// Returns 0, 1 (zero pivot) or 2 (non-finite column).
-__device__ __forceinline__ int team_lu(double* __restrict__ F, int ldj, int N, int& perm,
-                                       double& rdiag) {
-  const int lane = threadIdx.x;
-  perm = lane;
-  rdiag = 0.0;
-  for (int k = 0; k < N; ++k) {
-    // pivot search, lanes over rows
-    double a = -1.0;
-    if (lane >= k && lane < N) a = fabs(F[lane * ldj + k]);
-    if (__any(lane >= k && lane < N && !isfinite(a))) return 2;
-    const double best = wave_max(a);
-    if (!(best > 0.0)) return 1;
-    const int p = __builtin_amdgcn_readfirstlane(__ffsll((long long)__ballot(a == best)) - 1);
-    if (p != k) {
-      if (lane < N) {
-        const double t = F[k * ldj + lane];
-        F[k * ldj + lane] = F[p * ldj + lane];
-        F[p * ldj + lane] = t;
+// One column step of team_lu (column KC, a compile-time constant so that the
+// row stays in registers), followed by the steps of the later columns.
+template <int NMAX, int KC>
+__device__ __forceinline__ void team_lu_col(double (&A)[NMAX], int N, int& ord, double& rp_own, int& rc,
+                                            TeamLds& L) {
+  if constexpr (KC < NMAX) {
+    if (KC < N && rc == 0) {
+      const int lane = threadIdx.x;
+      const bool act = ord < 0;
+      const double a = fabs(A[KC]);
+      const double best = wave_max(act ? a : 0.0);
+      if (__any(act && !isfinite(a))) {
+        rc = 2;
+      } else if (!(best > 0.0)) {
+        rc = 1;
+      } else {
+        const double rb = 1.0 / best;           // 1/|pivot|, started before the pivot row is known
+        const int p =
+            __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)__ballot(act && a == best)) - 1);
+        const double rp = (bcast(A[KC], p) > 0.0) ? rb : -rb;   // 1/pivot exactly
+        double* row = L.prow + (KC & 1) * 64;   // alternate buffers: one barrier per column
+        if (lane == p) {
+          ord = KC;
+          rp_own = rp;
+          L.plane[KC] = lane;
+#pragma unroll
+          for (int j = KC + 1; j < NMAX; ++j) row[j] = A[j];
+        }
+        wsync();
+        // rows not yet used: multiplier, then the update of the rest of the row,
+        // eight columns at a time so that at most eight broadcast values are live
+        const double l = (ord < 0) ? A[KC] * rp : 0.0;
+        if (ord < 0) A[KC] = l;
+#pragma unroll
+        for (int j0 = KC + 1; j0 < NMAX; j0 += 8) {
+          double r[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (j0 + t < NMAX) r[t] = row[j0 + t];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (j0 + t < NMAX) A[j0 + t] -= l * r[t];
+        }
       }
-      const int pk = __builtin_amdgcn_readlane(perm, k), pp = __builtin_amdgcn_readlane(perm, p);
-      if (lane == k) perm = pp;
-      if (lane == p) perm = pk;
-      wsync();
     }
-    // multipliers, lanes over rows (held in lmul for the broadcast)
-    const double ukk = F[k * ldj + k];
-    const double rk = 1.0 / ukk;
-    if (lane == k) rdiag = rk;
-    double lmul = 0.0;
-    if (lane > k && lane < N) {
-      lmul = F[lane * ldj + k] / ukk;
-      F[lane * ldj + k] = lmul;
-    }
-    // trailing update, lanes over columns j > k, rows in chunks of 8
-    const bool col_active = lane > k && lane < N;
-    const double ukj = col_active ? F[k * ldj + lane] : 0.0;
-    double* col = F + lane;
-    for (int i0 = k + 1; i0 < N; i0 += 8) {
-      double v[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-        v[t] = (col_active && i0 + t < N) ? col[(i0 + t) * ldj] : 0.0;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int i = i0 + t < N ? i0 + t : N - 1;
-        v[t] -= bcast(lmul, i) * ukj;
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (col_active && i0 + t < N) col[(i0 + t) * ldj] = v[t];
-    }
-    wsync();
+    team_lu_col<NMAX, KC + 1>(A, N, ord, rp_own, rc, L);
   }
+}
+
+// LU with partial pivoting of M = d I - J, J the N x N matrix in LDS (row i at
+// F[i * ldj]), N <= NMAX.  Lane i loads row i of M into NMAX registers and the
+// elimination runs there with implicit pivoting: the pivot of column k is the
+// largest |M[i][k]| over the rows not yet used (ties to the lowest original
+// row), and its row reaches the other lanes through LDS.  The rows are then
+// stored over J in pivot order: row k of F holds row k of L below the
+// diagonal (unit diagonal implied) and row k of U from the diagonal on - the
+// factors of the textbook LU with explicit row swaps.  perm (lane-distributed)
+// receives the permutation (row k of the factors is row perm[k] of M); rdiag
+// receives 1 / U_kk in lane k.  Returns 0, 1 (zero pivot) or 2 (non-finite
+// pivot column); F is then partly overwritten.
+template <int NMAX>
+__device__ __forceinline__ int team_lu(double* __restrict__ F, int ldj, int N, double d, int& perm,
+                                       double& rdiag, TeamLds& L) {
+  const int lane = threadIdx.x;
+  const bool own = lane < N;
+  double A[NMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) A[j] = (own && j < N) ? (j == lane ? d : 0.0) - F[lane * ldj + j] : 0.0;
+  int ord = own ? -1 : NMAX;                  // pivot position of this lane's row; -1 while unused
+  double rp_own = 0.0;                        // 1 / (this row's pivot)
+  int rc = 0;
+  team_lu_col<NMAX, 0>(A, N, ord, rp_own, rc, L);
+  wsync();
+  if (rc) return rc;
+  if (own) {
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+      if (j < N) F[ord * ldj + j] = A[j];
+  }
+  wsync();
+  perm = own ? L.plane[lane] : lane;
+  rdiag = own ? gather(rp_own, perm) : 0.0;
+  wsync();
   return 0;
 }
 

@@ -78,6 +78,32 @@ def assert_parity(Tg, Yg, To, Yo, label, o=None, inputs=None, dt=None, max_frac=
     assert np.all(dY <= barY + 3 * envY), label
 
 
+def assert_h_parity(hg, ho, o, inputs, dt, max_frac=0.25):
+    """The returned step is the controller's proposal h clamp(0.9 err^(-1/4)),
+    with err the RMS of the embedded error estimate: a cancelled O(rtol)
+    quantity.  After hundreds of steps through a thermal runaway a
+    rounding-level change of the state moves err, and so this proposal, by
+    O(1).  So: the median agrees tightly, and every cell off by more than half
+    must be one whose oracle proposal itself moves by more than a tenth under
+    relative input changes of 1e-15 .. 1e-12.  (On the 256-cell small-mechanism
+    set the oracle's own proposal moves by more than a tenth on 51 cells and by
+    more than half on 36; max_frac bounds the share of such cells.)"""
+    rel = np.abs(hg - ho) / ho
+    assert np.median(rel) < 1e-3
+    bad = np.where(rel >= 0.5)[0]
+    if bad.size == 0:
+        return
+    assert bad.size <= max_frac * ho.size, "h: %d of %d cells off by > 50%%" % (bad.size, ho.size)
+    T, P, Y = inputs
+    hs = [o.integrate(T[bad] * (1.0 + e), P[bad], np.ascontiguousarray(Y[:, bad]), dt)["h"]
+          for e in (1e-15, -1e-15, 1e-14, -1e-14, 1e-13, 1e-12)]
+    hs = np.array(hs)
+    spread = (hs.max(0) - hs.min(0)) / ho[bad]
+    stiff = spread >= 0.1
+    assert np.all(stiff), "h: cells %s off by %s with oracle spread %s" % (
+        bad[~stiff], rel[bad][~stiff], spread[~stiff])
+
+
 def run_gpu(C, mech, T, P, Y, dt, mode="plain", h=None, **kw):
     opts = C.default_opts(mode=mode, **kw)
     hh = None if h is None else dev(h)
@@ -131,10 +157,7 @@ def test_small_parity_full_config(chem, small, mode):
     assert_parity(Tg, Yg, r["T"], r["Y"], "small", o, (T, P, Y), 1e-6)
     # hundreds of steps per cell: a few accept/reject decisions differ by rounding
     assert np.mean(ng == r["n_acc"]) >= 0.8
-    # the returned step is the controller's proposal, err^(-1/4) of an O(rtol)
-    # difference quantity: on these rounding-chaotic cells it agrees only loosely
-    rel = np.abs(hg - r["h"]) / r["h"]
-    assert np.median(rel) < 1e-3 and np.mean(rel < 0.5) > 0.95
+    assert_h_parity(hg, r["h"], o, (T, P, Y), 1e-6)
     mech.close()
 
 
@@ -192,6 +215,25 @@ def test_large_parity_small_batch(chem, large):
     r = o.integrate(T, P, Y, 1e-5)
     assert np.all(sg == 0)
     assert_parity(Tg, Yg, r["T"], r["Y"], "large", o, (T, P, Y), 1e-5, max_frac=0.03)
+    mech.close()
+
+
+@pytest.mark.parametrize("mode", ["plain", "persistent", "team", "team_persistent"])
+def test_dispatch_order_leaves_results_unchanged(chem, small, mode):
+    """Hottest-first dispatch only reorders the work: every cell's state, step
+    count, status and final h are bit-identical to the index-order run (3,000
+    cells over 900-2000 K, a ragged last block of the ordering kernels)."""
+    path, m, o = small
+    say("case: dispatch order", mode)
+    mech = chem.Mechanism(path)
+    T, P, Y = synth.states_small(m, n=3000, seed=11)
+    a = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode, order=0)
+    b = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode, order=1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    with pytest.raises(chem.ChemError) as ei:
+        run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode, order=2)
+    assert ei.value.code == chem.EINVAL
     mech.close()
 
 
