@@ -9,8 +9,11 @@ chem_integrate call over every cell with the inputs resident in HBM.
 Prints one JSON line (rank 0).  Extra keys: "roofline" for the integrator
 kernel (algorithmic FP64 flops per launch over its average launch duration,
 measured with HIP events on the launch stream), "cpu_baseline" (the CPU
-oracle on a bounded sample of the same cells, on this host's cores) and
-"modes" (cells/s of each launch mode of the library on this workload).
+oracle on a bounded sample of the same cells, on this host's cores), "modes"
+(cells/s of each launch mode of the library on this workload), "batching"
+(plain vs persistent launches on the batching mix, whose step counts differ
+by ~1000x between cells) and "adjoint" (discrete-adjoint vs forward time on
+the differentiation case).
 """
 from __future__ import annotations
 
@@ -61,6 +64,85 @@ def workload(name, synth, mech_dir):
     raise SystemExit("unknown workload %s" % name)
 
 
+def timed(fn, torch):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def batching(chem, synth, torch, np, mech_dir, n, dev):
+    """The batching mix (85 % cold, 10 % near ignition at stoichiometric
+    mixture fraction, 5 % burnt gas; dt = 1e-5 s) on n cells: cells/s of the
+    plain and persistent one-cell-per-thread launches (cells in index order
+    and hottest first) and of the one-wavefront-per-cell launches, one timed
+    call each after a warm-up call on 256 cells."""
+    path, m = synth.mechanism_file("ch4", mech_dir)
+    T, P, Y, kind = synth.states_batching(m, n, 203)
+    mech = chem.Mechanism(path, device=0)
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    Tt, Pt, Yt = d(T), d(P), d(Y)
+    out = {"workload": "CH4-shaped mechanism, %d cells drawn with the 1,048,576-cell batching recipe "
+                       "(85%% cold <800 K, 10%% stoichiometric 1100-1400 K, 5%% burnt gas), dt=1e-5 s" % n,
+           "cells": n, "cells_per_s": {}}
+    ns = None
+    runs = (("plain", 0), ("persistent", 0), ("plain", 1), ("persistent", 1), ("team", 1),
+            ("team_persistent", 1))
+    for mode, order in runs:
+        o = chem.default_opts(mode=mode, order=order)
+        chem.integrate(mech, Tt[:256], Pt[:256], Yt[:, :256].contiguous(), 1e-5, opts=o)
+        res = {}
+
+        def run():
+            res["r"] = chem.integrate(mech, Tt, Pt, Yt, 1e-5, opts=o)
+        el = timed(run, torch)
+        out["cells_per_s"][mode + ("" if order else "_index_order")] = round(n / el, 1)
+        ns = res["r"][3].cpu().numpy()
+        assert int((res["r"][4] != 0).sum()) == 0, "failed cells in the batching mix"
+    out["accepted_steps"] = {k: {"mean": round(float(ns[kind == i].mean()), 2), "max": int(ns[kind == i].max())}
+                             for i, k in enumerate(("cold", "igniting", "burnt"))}
+    cps = out["cells_per_s"]
+    # one cell per thread in index order is the plain baseline of the comparison
+    base = cps["plain_index_order"]
+    out["over_plain_index_order"] = {k: round(v / base, 3) for k, v in cps.items()}
+    mech.close()
+    return out
+
+
+def adjoint_cost(chem, synth, torch, np, mech_dir, n, dev):
+    """Differentiation case: n mixing-layer cells, dt = 1e-5 s, losses final T
+    and sum_k w_k Y_k; times of the plain forward call, the checkpointed
+    forward call (two passes) and the discrete adjoint (gradients with
+    respect to every ln A summed over cells, and the initial state)."""
+    path, m = synth.mechanism_file("ch4", mech_dir)
+    T, P, Y = synth.states_mixing(m, n, 205)
+    w = synth.loss_weights(m)
+    mech = chem.Mechanism(path, device=0)
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    Tt, Pt, Yt = d(T), d(P), d(Y)
+    gT = torch.ones(n, dtype=torch.float64, device=dev)
+    gY = d(np.repeat(w[:, None], n, 1))
+    chem.integrate(mech, Tt[:256], Pt[:256], Yt[:, :256].contiguous(), 1e-5)
+    t_fwd = min(timed(lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-5), torch) for _ in range(2))
+    res = {}
+
+    def fwd_ck():
+        res["ck"] = chem.integrate(mech, Tt, Pt, Yt, 1e-5, checkpoint=True)[5]
+    t_ck = timed(fwd_ck, torch)
+    ck = res["ck"]
+    recs = int(ck.records())
+    t_adj = timed(lambda: chem.adjoint(mech, ck, gT, gY, per_cell=False, initial=True), torch)
+    ck.close()
+    mech.close()
+    return {"workload": "CH4-shaped mechanism, %d mixing-layer cells, dt=1e-5 s, d(T_final + sum w_k Y_k)"
+                        "/d(ln A_j, T0, Y0)" % n,
+            "cells": n, "forward_ms": round(t_fwd * 1e3, 3), "forward_checkpointed_ms": round(t_ck * 1e3, 3),
+            "adjoint_ms": round(t_adj * 1e3, 3), "checkpoint_records": recs,
+            "adjoint_over_forward": round(t_adj / t_fwd, 3),
+            "gradient_over_forward": round((t_ck + t_adj) / t_fwd, 3)}
+
+
 def cpu_baseline(oracle, path, T, P, Y, dt, budget_s):
     """The oracle (as it is) on the first cells of the workload, in chunks of
     512, until about budget_s seconds of CPU work."""
@@ -89,6 +171,10 @@ def main():
                     help="other modes to time (thread-per-cell modes take one step)")
     ap.add_argument("--order", default="hot", choices=["hot", "index"],
                     help="dispatch order of the cells: hottest first (library default) or index order")
+    ap.add_argument("--batching-cells", type=int, default=65536,
+                    help="cells of the batching-mix comparison (0: skip)")
+    ap.add_argument("--adjoint-cells", type=int, default=16384,
+                    help="cells of the adjoint/forward cost measurement (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -186,13 +272,17 @@ def main():
         torch.cuda.synchronize()
         modes[mode] = round(n / ((time.perf_counter() - t) / reps), 1)
 
+    mech.close()
+    batch = batching(chem, synth, torch, np, mech_dir, a.batching_cells, dev) if a.batching_cells else None
+    adj = adjoint_cost(chem, synth, torch, np, mech_dir, a.adjoint_cells, dev) if a.adjoint_cells else None
+
     cpu = None
     if not a.no_cpu:
         import oracle
         cpu = cpu_baseline(oracle, path, T, P, Y, dt, a.cpu_seconds)
 
     out = {
-        "metric": "cells/s per split step at rtol 1e-6",
+        "metric": "cells/s per split step at rtol 1e-6 (plain vs persistent); adjoint/forward cost",
         "value": round(value, 1),
         "unit": "cells/s",
         "n_gpus": 1,
@@ -212,9 +302,10 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": modes,
+        "batching": batch,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
-    mech.close()
 
 
 if __name__ == "__main__":

@@ -55,7 +55,7 @@ struct IntParams {
   int64_t ld;
   unsigned int* queue;
   const int32_t* order;        // nullable: queue position -> cell
-  double* jsave;               // nullable: per work-group copy of J, [grid][N][64]
+  double* jsave;               // nullable: per work-group copy of J, [grid][N][N]
   unsigned long long* stats;   // nullable: attempts, accepted, rejected
   // adjoint checkpoint (nullable): per cell, accepted (Phi_n, h) records
   double* ck_data;          // [rec][N+1] per record, cell-major blocks
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
   const int lane = threadIdx.x;
   TeamLds L;
   L.bind(lds_raw, N);
-  double* const jsv = p.jsave ? p.jsave + (int64_t)blockIdx.x * N * 64 : nullptr;
+  double* const jsv = p.jsave ? p.jsave + (int64_t)blockIdx.x * N * N : nullptr;
   int64_t q;   // queue position
   if (PERSISTENT) {
     unsigned c0 = 0;
@@ -371,11 +371,11 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
         f1 = team_rhs_jac(M, P, phi, L, p.lnA);
         need_jac = false;
         if (jsv && lane < N)
-          for (int i = 0; i < N; ++i) jsv[i * 64 + lane] = L.J[i * ldj + lane];
+          for (int i = 0; i < N; ++i) jsv[i * N + lane] = L.J[i * ldj + lane];
       } else {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");   // own stores done, L1 invalidated
         if (lane < N)
-          for (int i = 0; i < N; ++i) L.J[i * ldj + lane] = jsv[i * 64 + lane];
+          for (int i = 0; i < N; ++i) L.J[i * ldj + lane] = jsv[i * N + lane];
         wsync();
       }
       // factors of M = I/(h gamma) - J over J
@@ -386,12 +386,12 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       if (rc == 0) {
         const double ih = 1.0 / hs;
         const double* F = L.J;
-        const double u1 = team_solve(F, ldj, N, perm, rdiag, f1);
+        const double u1 = team_solve<NMAX>(F, ldj, N, perm, rdiag, f1);
         double fs = team_rhs(M, P, phi + ROS4_A21 * u1, L, p.lnA);
-        const double u2 = team_solve(F, ldj, N, perm, rdiag, fs + (ROS4_C21 * ih) * u1);
+        const double u2 = team_solve<NMAX>(F, ldj, N, perm, rdiag, fs + (ROS4_C21 * ih) * u1);
         fs = team_rhs(M, P, phi + ROS4_A31 * u1 + ROS4_A32 * u2, L, p.lnA);
-        const double u3 = team_solve(F, ldj, N, perm, rdiag, fs + (ROS4_C31 * u1 + ROS4_C32 * u2) * ih);
-        const double u4 = team_solve(F, ldj, N, perm, rdiag,
+        const double u3 = team_solve<NMAX>(F, ldj, N, perm, rdiag, fs + (ROS4_C31 * u1 + ROS4_C32 * u2) * ih);
+        const double u4 = team_solve<NMAX>(F, ldj, N, perm, rdiag,
                                            fs + (ROS4_C41 * u1 + ROS4_C42 * u2 + ROS4_C43 * u3) * ih);
         ynew = phi + ROS4_M1 * u1 + ROS4_M2 * u2 + ROS4_M3 * u3 + ROS4_M4 * u4;
         const double e = ROS4_E1 * u1 + ROS4_E2 * u2 + ROS4_E3 * u3 + ROS4_E4 * u4;
@@ -477,6 +477,7 @@ struct AdjParams {
   int64_t n;
   const double* ck_data;   // per cell: accepted (Phi_n, h_n) records, then the final state
   const int64_t* ck_off;   // [n + 1]
+  const int32_t* order;    // [n] work-group -> cell
   const double* P;         // [n]
   const double* T0;        // [n] initial state (copy)
   const double* Y0;        // [K][n]
@@ -504,8 +505,8 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
   LA.bind2(lds_raw, vb, plane, N);
   LB.bind2(lds_raw + mat, vb, plane, N);
   LD.bind2((Dd*)lds_raw, (Dd*)vb, plane, N);
-  const int64_t cell = blockIdx.x;
-  if (cell >= a.n) return;
+  if ((int64_t)blockIdx.x >= a.n) return;
+  const int64_t cell = a.order[blockIdx.x];
   const double P = a.P[cell];
   const int64_t off = a.ck_off[cell];
   const int64_t cnt = a.ck_off[cell + 1] - off - 1;
@@ -550,14 +551,14 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
     wsync();
     const double ih = 1.0 / h;
     const double* F = LA.J;
-    const double u1 = team_solve(F, ldj, N, perm, rdiag, f1);
+    const double u1 = team_solve<NMAX>(F, ldj, N, perm, rdiag, f1);
     const double y2 = x + ROS4_A21 * u1;
     const double F2 = team_rhs(M, P, y2, LA, a.lnA);
-    const double u2 = team_solve(F, ldj, N, perm, rdiag, F2 + (ROS4_C21 * ih) * u1);
+    const double u2 = team_solve<NMAX>(F, ldj, N, perm, rdiag, F2 + (ROS4_C21 * ih) * u1);
     const double y3 = x + ROS4_A31 * u1 + ROS4_A32 * u2;
     const double F3 = team_rhs(M, P, y3, LA, a.lnA);
-    const double u3 = team_solve(F, ldj, N, perm, rdiag, F3 + (ROS4_C31 * u1 + ROS4_C32 * u2) * ih);
-    const double u4 = team_solve(F, ldj, N, perm, rdiag,
+    const double u3 = team_solve<NMAX>(F, ldj, N, perm, rdiag, F3 + (ROS4_C31 * u1 + ROS4_C32 * u2) * ih);
+    const double u4 = team_solve<NMAX>(F, ldj, N, perm, rdiag,
                                  F3 + (ROS4_C41 * u1 + ROS4_C42 * u2 + ROS4_C43 * u3) * ih);
     // ---- reverse
     double phib = lam;
@@ -779,7 +780,9 @@ struct chem_ckpt_s {
   double* Y0 = nullptr;
   double* lnA = nullptr;         // [Nr] copy of the ln A override, or null
   int64_t total = 0;             // records
+  int32_t* order = nullptr;      // [n] cells by decreasing record count (adjoint dispatch order)
   std::vector<int64_t> off_host;
+  std::vector<int32_t> order_host;
 };
 
 namespace {
@@ -1092,6 +1095,14 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   if (hipMalloc(&c->data, (size_t)c->total * (N + 1) * 8)) return fail(CHEM_ENOMEM);
   if (hipMemcpyAsync(c->off, c->off_host.data(), (n + 1) * 8, hipMemcpyHostToDevice, stream))
     return fail(CHEM_EHIP);
+  // the adjoint's cost per cell is its record count: longest first
+  c->order_host.resize(n);
+  for (int64_t i = 0; i < n; ++i) c->order_host[i] = (int32_t)i;
+  std::stable_sort(c->order_host.begin(), c->order_host.end(),
+                   [&](int32_t a, int32_t b) { return steps[a] > steps[b]; });
+  if (hipMalloc(&c->order, n * 4)) return fail(CHEM_ENOMEM);
+  if (hipMemcpyAsync(c->order, c->order_host.data(), n * 4, hipMemcpyHostToDevice, stream))
+    return fail(CHEM_EHIP);
   // pass 2: same inputs (the copies), the caller's outputs and h
   double* h2 = th;
   if (h_io) {
@@ -1213,7 +1224,7 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
       grid = (unsigned)std::min<int64_t>((int64_t)m->n_cu * per_cu, n);
       {
         std::lock_guard<std::mutex> g(m->mu);
-        rc = grow((void**)&w->jsave, &w->jsave_bytes, (size_t)grid * m->view.N * 64 * sizeof(double));
+        rc = grow((void**)&w->jsave, &w->jsave_bytes, (size_t)grid * m->view.N * m->view.N * sizeof(double));
         if (rc) return rc;
       }
       p.jsave = w->jsave;
@@ -1301,6 +1312,7 @@ int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, co
   a.n = n;
   a.ck_data = ckpt->data;
   a.ck_off = ckpt->off;
+  a.order = ckpt->order;
   a.P = ckpt->P;
   a.T0 = ckpt->T0;
   a.Y0 = ckpt->Y0;
@@ -1494,6 +1506,7 @@ void chem_ckpt_free(chem_ckpt_t c) {
   if (c->T0) (void)hipFree(c->T0);
   if (c->Y0) (void)hipFree(c->Y0);
   if (c->lnA) (void)hipFree(c->lnA);
+  if (c->order) (void)hipFree(c->order);
   delete c;
 }
 

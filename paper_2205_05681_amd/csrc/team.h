@@ -473,43 +473,56 @@ __device__ __forceinline__ int team_lu(double* __restrict__ F, int ldj, int N, d
   return 0;
 }
 
-// Solve M x = b with the factors of team_lu.  b and x are lane-distributed
-// (element i in lane i).
+// Solve M x = b with the factors of team_lu (row k of F holds row k of L and
+// of U in pivot order; perm and rdiag as returned).  b and x are
+// lane-distributed (element i in lane i; lanes >= N hold 0).  Every column
+// step is unrolled (NMAX >= N columns, the ones past N are zero), so the
+// broadcast of the finished element is a v_readlane with a constant lane and
+// the step's critical path is readlane -> FMA.  The row entries are read from
+// LDS eight at a time and masked to the triangle being applied; the backward
+// sweep applies columns of U scaled by 1/U_kk and multiplies by 1/U_ii at the
+// end (lane i's element is final once column i is reached).
+template <int NMAX>
 __device__ __forceinline__ double team_solve(const double* __restrict__ F, int ldj, int N, int perm,
                                              double rdiag, double b) {
   const int lane = threadIdx.x;
-  const double* row = F + (lane < N ? lane : 0) * ldj;
+  const bool own = lane < N;
+  const double* row = F + (own ? lane : 0) * ldj;
   b = gather(b, perm);                       // P b
-  // forward, unit lower triangle; k is wave-uniform, so the broadcast is a readlane
-  for (int k0 = 0; k0 < N - 1; k0 += 8) {
-    double l[8];
+  // forward: L y = P b (unit lower triangle)
 #pragma unroll
-    for (int t = 0; t < 8; ++t) l[t] = (k0 + t < N) ? row[k0 + t] : 0.0;
+  for (int k0 = 0; k0 < NMAX; k0 += 8) {
+    double l[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int k = k0 + t;
-      if (k < N - 1) {
-        const double yk = bcast(b, k);
-        if (lane > k && lane < N) b -= l[t] * yk;
-      }
+      const double v = row[k];   // in this work-group's LDS for every k < NMAX; masked by a select
+      l[t] = (own && k < lane) ? v : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + t;
+      if (k < NMAX - 1) b -= l[t] * bcast(b, k);
     }
   }
-  // backward, upper triangle
-  for (int k1 = N - 1; k1 >= 0; k1 -= 8) {
-    double u[8];
+  // backward: U x = y, with z_i -= (U_ik / U_kk) z_k and x_i = z_i / U_ii
 #pragma unroll
-    for (int t = 0; t < 8; ++t) u[t] = (k1 - t >= 0) ? row[k1 - t] : 0.0;
+  for (int k1 = NMAX - 1; k1 >= 0; k1 -= 8) {
+    double u[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int k = k1 - t;
-      if (k >= 0) {
-        const double xk = bcast(b, k) * bcast(rdiag, k);
-        if (lane == k) b = xk;
-        if (lane < k) b -= u[t] * xk;
-      }
+      const int kk = k >= 0 ? k : 0;
+      const double v = row[kk] * bcast(rdiag, kk);
+      u[t] = (own && k > lane && k < N) ? v : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k1 - t;
+      if (k > 0) b -= u[t] * bcast(b, k);
     }
   }
-  return b;
+  return own ? b * rdiag : 0.0;
 }
 
 }  // namespace chem
