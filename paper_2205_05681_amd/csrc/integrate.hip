@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       // factors of M = I/(h gamma) - J over J
       int perm;
       double rdiag;
-      const int rc = team_lu<NMAX>(L.J, ldj, N, 1.0 / (hs * ROS4_GAMMA), perm, rdiag, L);
+      const int rc = team_lu<NMAX>(L.J, ldj, N, 1.0 / (hs * ROS4_GAMMA), perm, rdiag);
       double err = 0.0, ynew = 0.0;
       if (rc == 0) {
         const double ih = 1.0 / hs;
@@ -544,7 +544,7 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
     const double f1 = team_rhs_jac<double>(M, P, x, LA, a.lnA);
     int perm;
     double rdiag;
-    team_lu<NMAX>(LA.J, ldj, N, 1.0 / (h * ROS4_GAMMA), perm, rdiag, LA);
+    team_lu<NMAX>(LA.J, ldj, N, 1.0 / (h * ROS4_GAMMA), perm, rdiag);
     if (lane < N) plane[perm] = lane;
     wsync();
     const int invperm = (lane < N) ? plane[lane] : lane;

@@ -9,9 +9,10 @@
 //     applied in one row-parallel and one column-parallel pass;
 //   * the LU of M = I/(h gamma) - J loads row i into lane i's registers and
 //     eliminates with implicit partial pivoting (rows stay in their lanes, the
-//     pivot order is recorded; the pivot search is a wave max-reduction plus
-//     a ballot, the pivot row is broadcast through LDS); the factors go back
-//     to LDS in pivot order for the triangular solves;
+//     pivot order is recorded; the pivot search is an exact wave max over the
+//     IEEE words of |a| plus a ballot, the pivot row is broadcast by
+//     v_readlane); the factors go back to LDS in pivot order for the
+//     triangular solves;
 //   * every controller decision is uniform over the wavefront.
 // Work-groups are one wavefront, so a work-group barrier is a wave barrier.
 #pragma once
@@ -94,13 +95,10 @@ struct TeamLdsT {
   S* dwdT;   // [64]
   S* dwdV;   // [64]
   S* vec;    // [64]       staging of a lane-distributed vector
-  S* prow;   // [2][64]    LU pivot-row broadcast; aliases dwdT and dwdV, which
-             //            only the Jacobian assembly uses
   int* plane;            // [64]
-  // Two layouts.  bind(): dwdT and dwdV first, at the start of the work-group's
-  // LDS, so that the LU's pivot-row buffer has a compile-time address; then the
-  // matrix, brow and the other vectors.  bind2(): the matrix at Jb and every
-  // vector at Vb (the adjoint's two matrix views share one vector block).
+  // Two layouts.  bind(): dwdT and dwdV first, then the matrix, brow and the
+  // other vectors.  bind2(): the matrix at Jb and every vector at Vb (the
+  // adjoint's two matrix views share one vector block).
   // elements of S after the matrix: brow and the vectors
   static __host__ __device__ size_t vec_elems(int N) { return (size_t)(N + 1) + 10 * 64; }
   static __host__ __device__ size_t doubles(int N) {
@@ -120,14 +118,12 @@ struct TeamLdsT {
     dwdT = tb + 64;
     dwdV = dwdT + 64;
     vec = dwdV + 64;
-    prow = dwdT;
     plane = pl;
   }
   __device__ void bind(double* base, int N) {
     S* b = (S*)base;
     dwdT = b;
     dwdV = b + 64;
-    prow = dwdT;
     J = b + 128;
     brow = J + (size_t)N * (N + 1);
     conc = brow + (N + 1);
@@ -320,6 +316,8 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
     wsum = wk;
     wcp = wk * cpk;
     S dvs = sc<S>(0.0);
+    // unrolled so that several LDS loads are in flight (latency-bound otherwise)
+#pragma unroll 8
     for (int m = 0; m < K - 1; ++m) {
       const S dn = row[m + 2] + t - gbk;
       dvs -= dn * L.conc[m];
@@ -346,20 +344,17 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
   if (lane < N) {
     const int c = lane;
     S ah = sc<S>(0.0), aw = sc<S>(0.0);
-    if (c >= 2) {
-      for (int k = 0; k < K; ++k) {
-        const S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-        const S d = row[c] * iV;           // d wdot_k / d n_m
-        ah += L.hrt[k] * RU * T * d;
-        aw += d;
-      }
-    } else {
-      const S* src = (c == 0) ? L.dwdT : L.dwdV;
-      for (int k = 0; k < K; ++k) {
-        const S d = src[k];
-        ah += L.hrt[k] * RU * T * d;
-        aw += d;
-      }
+    // d wdot_k / d Phi_c: column c of row k for the species columns (per unit
+    // n, so times 1/V), dwdT / dwdV for the T and V columns; one loop for all
+    // lanes, the address chosen per lane
+    const S* src = (c == 0) ? L.dwdT : L.dwdV;
+    const S scale = (c >= 2) ? iV : sc<S>(1.0);
+#pragma unroll 8
+    for (int k = 0; k < K; ++k) {
+      const S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+      const S d = ((c >= 2) ? row[c] : src[k]) * scale;
+      ah += L.hrt[k] * RU * T * d;
+      aw += d;
     }
     const S cpb = L.cpr[K - 1] * RU;
     S dD, dTd, dVd;
@@ -387,78 +382,88 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
   return f;
 }
 
+// Largest of a non-negative 32-bit key over the 64 lanes (DPP inside rows,
+// then the four rows by v_readlane).
+__device__ __forceinline__ unsigned umax32(unsigned a, unsigned b) { return a > b ? a : b; }
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp32(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = umax32(v, dpp32<DPP_QUAD_1032>(v));
+  v = umax32(v, dpp32<DPP_QUAD_2301>(v));
+  v = umax32(v, dpp32<DPP_ROW_HALF_MIRROR>(v));
+  v = umax32(v, dpp32<DPP_ROW_MIRROR>(v));
+  const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return umax32(umax32(a, b), umax32(c, d));
+}
+
 // One column step of team_lu (column KC, a compile-time constant so that the
-// row stays in registers), followed by the steps of the later columns.
+// row stays in registers), followed by the steps of the later columns.  No
+// branches: the pivot row is broadcast by v_readlane and the failure code is
+// accumulated, so the scheduler can overlap the next column's pivot search
+// with the rest of this column's update.
 template <int NMAX, int KC>
-__device__ __forceinline__ void team_lu_col(double (&A)[NMAX], int N, int& ord, double& rp_own, int& rc,
-                                            TeamLds& L) {
+__device__ __forceinline__ void team_lu_col(double (&A)[NMAX], int& ord, double& rp_own, int& pv,
+                                            int& rc) {
   if constexpr (KC < NMAX) {
-    if (KC < N && rc == 0) {
-      const int lane = threadIdx.x;
-      const bool act = ord < 0;
-      const double a = fabs(A[KC]);
-      const double best = wave_max(act ? a : 0.0);
-      if (__any(act && !isfinite(a))) {
-        rc = 2;
-      } else if (!(best > 0.0)) {
-        rc = 1;
-      } else {
-        const double rb = 1.0 / best;           // 1/|pivot|, started before the pivot row is known
-        const int p =
-            __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)__ballot(act && a == best)) - 1);
-        const double rp = (bcast(A[KC], p) > 0.0) ? rb : -rb;   // 1/pivot exactly
-        double* row = L.prow + (KC & 1) * 64;   // alternate buffers: one barrier per column
-        if (lane == p) {
-          ord = KC;
-          rp_own = rp;
-          L.plane[KC] = lane;
+    const int lane = threadIdx.x;
+    const bool act = ord < 0;
+    // the largest |A[KC]| over the rows not yet used, exactly: the IEEE words
+    // of a non-negative double order like the value, high word first
+    const double a = fabs(A[KC]);
+    const unsigned hi = act ? (unsigned)__double2hiint(a) : 0u;
+    const unsigned lo = (unsigned)__double2loint(a);
+    const unsigned mhi = wave_max_u32(hi);
+    const bool cand = act && hi == mhi;
+    const unsigned mlo = wave_max_u32(cand ? lo : 0u);
+    const int p = __builtin_amdgcn_readfirstlane(
+        __ffsll((unsigned long long)__ballot(cand && lo == mlo)) - 1);   // ties: lowest lane
+    const bool nonfinite = __any(act && hi >= 0x7FF00000u);
+    const int code = nonfinite ? 2 : ((mhi | mlo) == 0u ? 1 : 0);
+    rc = (rc == 0) ? code : rc;
+    const double rp = 1.0 / bcast(A[KC], p);
+    const bool is_p = lane == p;
+    const bool upd = act && !is_p;
+    const double l = upd ? A[KC] * rp : 0.0;
+    A[KC] = upd ? l : A[KC];
+    ord = is_p ? KC : ord;
+    rp_own = is_p ? rp : rp_own;
+    pv = (lane == KC) ? p : pv;
 #pragma unroll
-          for (int j = KC + 1; j < NMAX; ++j) row[j] = A[j];
-        }
-        wsync();
-        // rows not yet used: multiplier, then the update of the rest of the row,
-        // eight columns at a time so that at most eight broadcast values are live
-        const double l = (ord < 0) ? A[KC] * rp : 0.0;
-        if (ord < 0) A[KC] = l;
-#pragma unroll
-        for (int j0 = KC + 1; j0 < NMAX; j0 += 8) {
-          double r[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t)
-            if (j0 + t < NMAX) r[t] = row[j0 + t];
-#pragma unroll
-          for (int t = 0; t < 8; ++t)
-            if (j0 + t < NMAX) A[j0 + t] -= l * r[t];
-        }
-      }
-    }
-    team_lu_col<NMAX, KC + 1>(A, N, ord, rp_own, rc, L);
+    for (int j = KC + 1; j < NMAX; ++j) A[j] -= l * bcast(A[j], p);
+    team_lu_col<NMAX, KC + 1>(A, ord, rp_own, pv, rc);
   }
 }
 
 // LU with partial pivoting of M = d I - J, J the N x N matrix in LDS (row i at
-// F[i * ldj]), N <= NMAX.  Lane i loads row i of M into NMAX registers and the
+// F[i * ldj]), N <= NMAX.  Lane i loads row i of M into NMAX registers (lanes
+// N..NMAX-1 hold identity rows, so every column step is the same) and the
 // elimination runs there with implicit pivoting: the pivot of column k is the
 // largest |M[i][k]| over the rows not yet used (ties to the lowest original
-// row), and its row reaches the other lanes through LDS.  The rows are then
-// stored over J in pivot order: row k of F holds row k of L below the
-// diagonal (unit diagonal implied) and row k of U from the diagonal on - the
-// factors of the textbook LU with explicit row swaps.  perm (lane-distributed)
-// receives the permutation (row k of the factors is row perm[k] of M); rdiag
-// receives 1 / U_kk in lane k.  Returns 0, 1 (zero pivot) or 2 (non-finite
-// pivot column); F is then partly overwritten.
+// row).  The rows are then stored over J in pivot order: row k of F holds row k
+// of L below the diagonal (unit diagonal implied) and row k of U from the
+// diagonal on - the factors of the textbook LU with explicit row swaps.  perm
+// (lane-distributed) receives the permutation (row k of the factors is row
+// perm[k] of M); rdiag receives 1 / U_kk in lane k.  Returns 0, 1 (zero pivot)
+// or 2 (non-finite pivot column), the first failure in column order; F is
+// untouched unless 0 is returned.
 template <int NMAX>
 __device__ __forceinline__ int team_lu(double* __restrict__ F, int ldj, int N, double d, int& perm,
-                                       double& rdiag, TeamLds& L) {
+                                       double& rdiag) {
   const int lane = threadIdx.x;
   const bool own = lane < N;
   double A[NMAX];
 #pragma unroll
-  for (int j = 0; j < NMAX; ++j) A[j] = (own && j < N) ? (j == lane ? d : 0.0) - F[lane * ldj + j] : 0.0;
-  int ord = own ? -1 : NMAX;                  // pivot position of this lane's row; -1 while unused
+  for (int j = 0; j < NMAX; ++j) {
+    const double m = (own && j < N) ? (j == lane ? d : 0.0) - F[lane * ldj + j] : 0.0;
+    A[j] = (!own && lane < NMAX && j == lane) ? 1.0 : m;
+  }
+  int ord = lane < NMAX ? -1 : NMAX;          // pivot position of this lane's row; -1 while unused
   double rp_own = 0.0;                        // 1 / (this row's pivot)
-  int rc = 0;
-  team_lu_col<NMAX, 0>(A, N, ord, rp_own, rc, L);
+  int pv = lane, rc = 0;                      // lane k: the row pivoted at step k
+  team_lu_col<NMAX, 0>(A, ord, rp_own, pv, rc);
   wsync();
   if (rc) return rc;
   if (own) {
@@ -467,9 +472,8 @@ __device__ __forceinline__ int team_lu(double* __restrict__ F, int ldj, int N, d
       if (j < N) F[ord * ldj + j] = A[j];
   }
   wsync();
-  perm = own ? L.plane[lane] : lane;
-  rdiag = own ? gather(rp_own, perm) : 0.0;
-  wsync();
+  perm = own ? pv : lane;
+  rdiag = own ? gather(rp_own, pv) : 0.0;
   return 0;
 }
 

@@ -128,6 +128,40 @@ def test_adjoint_matches_central_differences(case, ch4):
                 assert g[j] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(g).max()), (c, loss, j)
 
 
+def test_full_size_adjoint_sampled(chem, ch4):
+    """The differentiation case at its full size (16,384 cells, dt = 1e-5 s)
+    in the benchmark's launch: per-cell gradients of sum_k w_k Y_k for six
+    cells (the three with the most steps, three at random) against the
+    oracle's tangent along the GPU's own steps, and the summed gradient
+    against the sum of the per-cell ones."""
+    path, m, o = ch4
+    say("case: adjoint, ch4 mechanism, 16384 cells, dt=1e-5")
+    T, P, Y = synth.states_mixing(m, 16384, 205)
+    w = synth.loss_weights(m)
+    n = T.size
+    mech = chem.Mechanism(path)
+    T1, Y1, h1, ns, st, ck = chem.integrate(mech, dev(T), dev(P), dev(Y), 1e-5, checkpoint=True)
+    gT = torch.zeros(n, dtype=torch.float64, device="cuda")
+    gY = dev(np.repeat(w[:, None], n, 1))
+    g, _, _ = chem.adjoint(mech, ck, gT, gY, per_cell=True, initial=False)
+    gs, _, _ = chem.adjoint(mech, ck, gT, gY, per_cell=False, initial=False)
+    torch.cuda.synchronize()
+    off, rec = ck.export()
+    ck.close()
+    mech.close()
+    assert np.all(st.cpu().numpy() == 0)
+    g = g.cpu().numpy()
+    assert np.allclose(gs.cpu().numpy(), g.sum(1), rtol=1e-12, atol=1e-300)
+    nsn = ns.cpu().numpy()
+    rng = np.random.default_rng(11)
+    cells = np.unique(np.r_[np.argsort(-nsn)[:3], rng.choice(n, 3, replace=False)])
+    for c in cells:
+        hs = rec[off[c]:off[c + 1] - 1, -1].copy()
+        v = rng.normal(size=len(m.reactions))
+        dT, dY = o.tangent(T[c], P[c], Y[:, c], hs, v_lnA=v)
+        assert g[:, c] @ v == pytest.approx(w @ dY, rel=1e-6, abs=1e-9 * np.abs(g[:, c]).sum() + 1e-300), c
+
+
 def test_cell_sum_is_deterministic_reduction(case):
     assert np.allclose(case["gsum"], case["g2"].sum(1), rtol=1e-12, atol=1e-300)
 

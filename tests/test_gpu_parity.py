@@ -247,6 +247,31 @@ def test_ch4_full_size_sampled(chem, ch4):
     mech.close()
 
 
+def test_batching_full_size_sampled(chem, ch4):
+    """The batching mix at its full size, 1,048,576 cells (85 % cold, 10 %
+    igniting, 5 % burnt gas; dt = 1e-5 s), in the default launch; 48 cells
+    re-run on the oracle: 24 at random, the 12 with the most steps and 12 more
+    igniting ones."""
+    path, m, o = ch4
+    say("case: batching mix, 1048576 cells, auto launch")
+    T, P, Y, kind = synth.states_batching(m, 1048576, 203)
+    mech = chem.Mechanism(path)
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-5, mode="auto")
+    mech.close()
+    assert np.all(sg == 0)
+    rng = np.random.default_rng(3)
+    ign = np.where(kind == 1)[0]
+    idx = np.unique(np.r_[rng.choice(T.size, 24, replace=False), np.argsort(-ng)[:12],
+                          rng.choice(ign, 12, replace=False)])
+    Ts, Ps, Ys = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+    r = o.integrate(Ts, Ps, Ys, 1e-5)
+    assert np.all(r["status"] == 0)
+    assert_parity(Tg[idx], Yg[:, idx], r["T"], r["Y"], "batching full", o, (Ts, Ps, Ys), 1e-5, max_frac=0.1)
+    assert_steps_parity(ng[idx], r["n_acc"], o, (Ts, Ps, Ys), 1e-5, max_frac=0.2)
+    # the mix spans two orders of magnitude in step count
+    assert ng[kind == 0].mean() < 5 and ng[kind == 1].mean() > 50
+
+
 def test_large_parity_small_batch(chem, large):
     path, m, o = large
     say("case: large mechanism, 130 cells, plain")
