@@ -251,51 +251,64 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
     const int32_t* nu = M.rnu + 6 * j;
     const int nr = info[1], np = info[2];
     const S dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
+    // participant slots 0..2 (reactants) and 3..5 (products), with compile-time
+    // bounds: an unused slot has coefficient 0, and its updates go to this
+    // lane's own dummy cell (dwdT is written only after this loop)
+    S* const dummy = L.dwdT + lane;
+    int ks[6], nus[6];
+    bool on[6];
+    S cs[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      on[q] = (q < 3) ? (q < nr) : (q - 3 < np);
+      ks[q] = on[q] ? sp[q] : 0;
+      nus[q] = on[q] ? nu[q] : 0;
+      cs[q] = L.conc[ks[q]];
+    }
+    // d q / d C of slot q: the mass-action product of its side with the power
+    // of C_q lowered by one (the same multiplications, in the same order, as a
+    // loop over the side's species)
     S dq[6];
-    int ms[6];
-    int nm = 0;
-    for (int i = 0; i < nr; ++i) {
-      S d = r.kf;
-      for (int l = 0; l < nr; ++l) {
-        const S c = L.conc[sp[l]];
-        const int v = (l == i) ? nu[l] - 1 : nu[l];
-        if (v >= 1) d *= c;
-        if (v >= 2) d *= c;
-        if (v >= 3) d *= c;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int s0 = q < 3 ? 0 : 3;
+      S d = (q < 3) ? r.kf : r.kr;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const int v = (s0 + l == q) ? nus[s0 + l] - 1 : nus[s0 + l];
+        const S c = cs[s0 + l];
+        d = (v >= 1) ? d * c : d;
+        d = (v >= 2) ? d * c : d;
+        d = (v >= 3) ? d * c : d;
       }
-      ms[nm] = sp[i];
-      dq[nm++] = d * (double)nu[i];
+      dq[q] = d * (double)(q < 3 ? nus[q] : -nus[q]);
     }
-    for (int i = 0; i < np; ++i) {
-      S d = r.kr;
-      for (int l = 0; l < np; ++l) {
-        const S c = L.conc[sp[3 + l]];
-        const int v = (l == i) ? nu[3 + l] - 1 : nu[3 + l];
-        if (v >= 1) d *= c;
-        if (v >= 2) d *= c;
-        if (v >= 3) d *= c;
+    // scatter into row k = ks[q] of G (T column, species columns, bath column)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int k = ks[q];
+      const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
+      S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+      lds_add(on[q] ? &L.wdot[k] : dummy, vk * r.q);
+      lds_add(on[q] ? &row[0] : dummy, vk * dqdT);
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int m = ks[t];
+        S* dst = (m == K - 1) ? &L.gb[k] : &row[m + 2];
+        lds_add((on[q] && on[t]) ? dst : dummy, vk * dq[t]);
       }
-      ms[nm] = sp[3 + i];
-      dq[nm++] = d * (double)-nu[3 + i];
     }
-    for (int side = 0; side < 2; ++side) {
-      const int cnt = side ? np : nr;
-      for (int i = 0; i < cnt; ++i) {
-        const int k = sp[3 * side + i];
-        const double vk = side ? (double)nu[3 + i] : -(double)nu[i];
+    if (info[0] != RX_ELEM) {
+      // third body and falloff: the uniform [M] part and the efficiency columns
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int k = ks[q];
+        const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
         S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-        lds_add(&L.wdot[k], vk * r.q);
-        lds_add(&row[0], vk * dqdT);
-        for (int t = 0; t < nm; ++t) {
-          const int m = ms[t];
-          lds_add((m == K - 1) ? &L.gb[k] : &row[m + 2], vk * dq[t]);
-        }
-        if (info[0] != RX_ELEM) {
-          lds_add(&L.tb[k], vk * r.beta);
-          for (int e = info[3]; e < info[4]; ++e) {
-            const int m = M.eff_idx[e];
-            lds_add((m == K - 1) ? &L.gb[k] : &row[m + 2], (vk * M.eff_am1[e]) * r.beta);
-          }
+        lds_add(on[q] ? &L.tb[k] : dummy, vk * r.beta);
+        for (int e = info[3]; e < info[4]; ++e) {
+          const int m = M.eff_idx[e];
+          lds_add(on[q] ? ((m == K - 1) ? &L.gb[k] : &row[m + 2]) : dummy, (vk * M.eff_am1[e]) * r.beta);
         }
       }
     }

@@ -272,6 +272,25 @@ def test_batching_full_size_sampled(chem, ch4):
     assert ng[kind == 0].mean() < 5 and ng[kind == 1].mean() > 50
 
 
+def test_large_full_size_sampled(chem, large):
+    """The 111-species mechanism at its full size, 262,144 mixing-layer cells
+    (dt = 1e-5 s), in the default launch (one cell per thread, N > 64); 64
+    cells re-run on the oracle."""
+    path, m, o = large
+    say("case: large mechanism, 262144 cells, auto launch")
+    T, P, Y = synth.states_mixing(m, 262144, 204)
+    mech = chem.Mechanism(path)
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-5, mode="auto")
+    mech.close()
+    assert np.all(sg == 0)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.r_[rng.choice(T.size, 56, replace=False), np.argsort(-T)[:8]])
+    Ts, Ps, Ys = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+    r = o.integrate(Ts, Ps, Ys, 1e-5)
+    assert_parity(Tg[idx], Yg[:, idx], r["T"], r["Y"], "large full", o, (Ts, Ps, Ys), 1e-5, max_frac=0.05)
+    assert_steps_parity(ng[idx], r["n_acc"], o, (Ts, Ps, Ys), 1e-5, max_frac=0.05)
+
+
 def test_large_parity_small_batch(chem, large):
     path, m, o = large
     say("case: large mechanism, 130 cells, plain")
