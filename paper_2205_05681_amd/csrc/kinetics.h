@@ -148,16 +148,42 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S
   const int32_t* sp = M.rspec + 6 * j;
   const int32_t* nu = M.rnu + 6 * j;
   const double* ar = M.arr + 4 * j;
+  // Every field of the reaction is read up front and unconditionally (all six
+  // species slots exist, unused ones hold 0), so the loads overlap instead of
+  // following the data-dependent control flow one round trip at a time.
+  int spv[6], nuv[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    spv[q] = sp[q];
+    nuv[q] = nu[q];
+  }
   const int type = info[0], nr = info[1], np = info[2];
   const double lnA = lnA_over ? lnA_over[M.rorig[j]] : ar[0];
   const double b = ar[1], th = ar[2], dnu = ar[3];
+  S cq[6], gq[6], hq[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    cq[q] = conc[spv[q]];
+    gq[q] = gib[spv[q]];
+    hq[q] = want_deriv ? hrt[spv[q]] : sc<S>(0.0);
+  }
   const S lnkinf = lnA + b * lnT - th * iT;
   const S kinf = exp(lnkinf);
   const S dlnkinf = (b + th * iT) * iT;
   S k = kinf, dlnk = dlnkinf, dk_dM = sc<S>(0.0);
   if (type != RX_ELEM) {
+    // [M] = sum C + sum (alpha - 1) C over the listed efficiencies: the first
+    // four unrolled (loads issued together), any further ones in a loop
     S Mc = ctot;
-    for (int e = info[3]; e < info[4]; ++e) Mc += M.eff_am1[e] * conc[M.eff_idx[e]];
+    const int e0 = info[3], e1 = info[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = (e0 + t < e1) ? e0 + t : e0;   // in the table, or its padding when e0 == e1
+      const double am1 = M.eff_am1[e];
+      const S c = conc[M.eff_idx[e]];
+      if (e0 + t < e1) Mc += am1 * c;
+    }
+    for (int e = e0 + 4; e < e1; ++e) Mc += M.eff_am1[e] * conc[M.eff_idx[e]];
     if (type == RX_THIRD) {
       k = kinf * Mc;
       dk_dM = kinf;
@@ -170,9 +196,9 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S
       S F = sc<S>(1.0), dlnF_dlnPr = sc<S>(0.0), dlnF_dT_fc = sc<S>(0.0);
       if (type == RX_TROE) {
         const double a = f[3], T3 = f[4], T1 = f[5], T2 = f[6];
-        const S e3 = exp(-T * (1.0 / T3)), e1 = exp(-T * (1.0 / T1));
+        const S e3 = exp(-T * (1.0 / T3)), e1x = exp(-T * (1.0 / T1));
         const S e2 = T2 > 0.0 ? exp(-T2 * iT) : sc<S>(0.0);
-        const S Fc = (1.0 - a) * e3 + a * e1 + e2;
+        const S Fc = (1.0 - a) * e3 + a * e1x + e2;
         const S lFc = log10(Fc);
         const S c = -0.4 - 0.67 * lFc, n = 0.75 - 1.27 * lFc;
         const bool tiny = !(val(Pr) > 1e-300);
@@ -186,7 +212,7 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S
           const S dydx = n / (den * den), dydn = -x / (den * den);
           dlnF_dlnPr = tiny ? sc<S>(0.0) : dLdy * dydx;
           const S dLdlFc = 1.0 / opy + dLdy * (dydx * -0.67 + dydn * -1.27);
-          const S dFc = -(1.0 - a) * (1.0 / T3) * e3 - a * (1.0 / T1) * e1 +
+          const S dFc = -(1.0 - a) * (1.0 / T3) * e3 - a * (1.0 / T1) * e1x +
                         (T2 > 0.0 ? T2 * iT * iT * e2 : sc<S>(0.0));
           dlnF_dT_fc = dLdlFc * dFc / Fc;
         }
@@ -200,23 +226,29 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S
       }
     }
   }
+  // sums over the sides (reactants, then products, in slot order) and the
+  // mass-action products; an unused slot contributes nothing
   S sg = sc<S>(0.0), sh = sc<S>(0.0);
   S rf = sc<S>(1.0), rr = sc<S>(1.0);
-  for (int i = 0; i < nr; ++i) {
-    const int s = sp[i];
-    const double v = nu[i];
-    sg -= v * gib[s];
-    if (want_deriv) sh -= v * hrt[s];
-    const S cs = conc[s];
-    rf *= (nu[i] == 1) ? cs : (nu[i] == 2 ? cs * cs : cs * cs * cs);
+#pragma unroll
+  for (int i = 0; i < MAX_SIDE; ++i) {
+    if (i < nr) {
+      const double v = nuv[i];
+      sg -= v * gq[i];
+      if (want_deriv) sh -= v * hq[i];
+      const S cs = cq[i];
+      rf *= (nuv[i] == 1) ? cs : (nuv[i] == 2 ? cs * cs : cs * cs * cs);
+    }
   }
-  for (int i = 0; i < np; ++i) {
-    const int s = sp[3 + i];
-    const double v = nu[3 + i];
-    sg += v * gib[s];
-    if (want_deriv) sh += v * hrt[s];
-    const S cs = conc[s];
-    rr *= (nu[3 + i] == 1) ? cs : (nu[3 + i] == 2 ? cs * cs : cs * cs * cs);
+#pragma unroll
+  for (int i = 0; i < MAX_SIDE; ++i) {
+    if (i < np) {
+      const double v = nuv[3 + i];
+      sg += v * gq[3 + i];
+      if (want_deriv) sh += v * hq[3 + i];
+      const S cs = cq[3 + i];
+      rr *= (nuv[3 + i] == 1) ? cs : (nuv[3 + i] == 2 ? cs * cs : cs * cs * cs);
+    }
   }
   const S lnKc = sg + dnu * log(PATM / (RU * T));
   const S kr = k * exp(-lnKc);

@@ -165,7 +165,10 @@ __device__ __forceinline__ void team_state(const MechView& M, double P, S y, Tea
   if (lane < K) L.conc[lane] = c;
   S dcp = sc<S>(0.0);
   if (lane < K) {
-    const double* cf = M.nasa + 15 * lane;
+    // all fifteen coefficients read together, then the range selected
+    double cf[15];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) cf[i] = M.nasa[15 * lane + i];
     const bool lo = val(T) < cf[0];
     const double a0 = lo ? cf[1] : cf[8], a1 = lo ? cf[2] : cf[9], a2 = lo ? cf[3] : cf[10],
                  a3 = lo ? cf[4] : cf[11], a4 = lo ? cf[5] : cf[12], a5 = lo ? cf[6] : cf[13],
@@ -200,8 +203,12 @@ __device__ __forceinline__ double team_rhs(const MechView& M, double P, double y
     const int32_t* info = M.rinfo + 8 * j;
     const int32_t* sp = M.rspec + 6 * j;
     const int32_t* nu = M.rnu + 6 * j;
-    for (int i = 0; i < info[1]; ++i) atomicAdd(&L.wdot[sp[i]], -nu[i] * r.q);
-    for (int i = 0; i < info[2]; ++i) atomicAdd(&L.wdot[sp[3 + i]], nu[3 + i] * r.q);
+    // slots with compile-time bounds, loads unconditional (unused slots hold 0)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int sq = sp[q], nq = nu[q];
+      if ((q < 3) ? (q < info[1]) : (q - 3 < info[2])) atomicAdd(&L.wdot[sq], (q < 3 ? -nq : nq) * r.q);
+    }
   }
   wsync();
   double w = 0.0, num = 0.0, den = 0.0;
@@ -261,8 +268,8 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       on[q] = (q < 3) ? (q < nr) : (q - 3 < np);
-      ks[q] = on[q] ? sp[q] : 0;
-      nus[q] = on[q] ? nu[q] : 0;
+      ks[q] = sp[q];           // unused slots hold species 0 and coefficient 0
+      nus[q] = nu[q];
       cs[q] = L.conc[ks[q]];
     }
     // d q / d C of slot q: the mass-action product of its side with the power
@@ -299,14 +306,30 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
       }
     }
     if (info[0] != RX_ELEM) {
-      // third body and falloff: the uniform [M] part and the efficiency columns
+      // third body and falloff: the uniform [M] part and the efficiency
+      // columns; the first four efficiencies are read together up front, any
+      // further ones in a loop
+      const int e0 = info[3], e1 = info[4];
+      int em[4];
+      double ea[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int e = (e0 + t < e1) ? e0 + t : e0;   // in the table, or its padding when e0 == e1
+        em[t] = M.eff_idx[e];
+        ea[t] = M.eff_am1[e];
+      }
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         const int k = ks[q];
         const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
         S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
         lds_add(on[q] ? &L.tb[k] : dummy, vk * r.beta);
-        for (int e = info[3]; e < info[4]; ++e) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          S* dst = (em[t] == K - 1) ? &L.gb[k] : &row[em[t] + 2];
+          lds_add((on[q] && e0 + t < e1) ? dst : dummy, (vk * ea[t]) * r.beta);
+        }
+        for (int e = e0 + 4; e < e1; ++e) {
           const int m = M.eff_idx[e];
           lds_add(on[q] ? ((m == K - 1) ? &L.gb[k] : &row[m + 2]) : dummy, (vk * M.eff_am1[e]) * r.beta);
         }
