@@ -447,17 +447,22 @@ __device__ __forceinline__ void team_lu_col(double (&A)[NMAX], int& ord, double&
     const int lane = threadIdx.x;
     const bool act = ord < 0;
     // the largest |A[KC]| over the rows not yet used, exactly: the IEEE words
-    // of a non-negative double order like the value, high word first
+    // of a non-negative double order like the value, high word first (the low
+    // words are compared only when the high words tie)
     const double a = fabs(A[KC]);
     const unsigned hi = act ? (unsigned)__double2hiint(a) : 0u;
     const unsigned lo = (unsigned)__double2loint(a);
     const unsigned mhi = wave_max_u32(hi);
     const bool cand = act && hi == mhi;
-    const unsigned mlo = wave_max_u32(cand ? lo : 0u);
-    const int p = __builtin_amdgcn_readfirstlane(
-        __ffsll((unsigned long long)__ballot(cand && lo == mlo)) - 1);   // ties: lowest lane
+    unsigned long long sel = __ballot(cand);
+    if (__builtin_popcountll(sel) > 1) {   // several rows share the high word: compare the low words
+      const unsigned mlo = wave_max_u32(cand ? lo : 0u);
+      sel = __ballot(cand && lo == mlo);
+    }
+    const int p = __builtin_amdgcn_readfirstlane(__ffsll(sel) - 1);   // ties: lowest lane
     const bool nonfinite = __any(act && hi >= 0x7FF00000u);
-    const int code = nonfinite ? 2 : ((mhi | mlo) == 0u ? 1 : 0);
+    const bool zero = mhi == 0u && __builtin_amdgcn_readlane((int)lo, p) == 0;   // largest |a| is 0
+    const int code = nonfinite ? 2 : (zero ? 1 : 0);
     rc = (rc == 0) ? code : rc;
     const double rp = 1.0 / bcast(A[KC], p);
     const bool is_p = lane == p;
