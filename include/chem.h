@@ -137,8 +137,9 @@ int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const dou
  *                       [Nr][n] per cell (per_cell = 1), overwritten
  *   gT0[n], gY0[K][ldY] nullable: dL/dT_in, dL/dY_in
  * One wavefront per cell: needs N <= 64 and the per-cell LDS (two N x (N+1)
- * matrices, dual vectors and Nr accumulators) within 64 KiB, else
- * CHEM_EUNSUPPORTED.  The sum over cells is taken in a fixed order.
+ * matrices, dual vectors and Nr accumulators) within the device's LDS per
+ * work-group (160 KiB on MI355X), else CHEM_EUNSUPPORTED.  The sum over
+ * cells is taken in a fixed order.
  * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM, CHEM_EUNSUPPORTED. */
 int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, const double* gY,
                            int64_t ldY, double* g_lnA, int32_t per_cell, double* gT0,

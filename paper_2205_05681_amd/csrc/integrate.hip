@@ -1303,8 +1303,10 @@ int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, co
   const int64_t n = ckpt->n;
   if (N > 64) return CHEM_EUNSUPPORTED;
   const size_t lds = (2 * (size_t)N * (N + 1) + 2 * TeamLdsT<double>::vec_elems(N) + 32 + Nr) * 8;
-  if (lds > 65536) return CHEM_EUNSUPPORTED;
   HIPCHECK(hipSetDevice(m->device));
+  int lds_max = 0;
+  HIPCHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device));
+  if (lds > (size_t)lds_max) return CHEM_EUNSUPPORTED;
   double* g_cell = per_cell ? g_lnA : nullptr;
   if (!per_cell && hipMalloc(&g_cell, (size_t)Nr * n * 8)) return CHEM_ENOMEM;
   AdjParams a;
@@ -1328,6 +1330,8 @@ int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, co
                             : N <= 48 ? adjoint_team_kernel<48>
                             : N <= 56 ? adjoint_team_kernel<56>
                                       : adjoint_team_kernel<64>;
+  if (lds > 65536)   // above the default dynamic-LDS limit of a launch
+    HIPCHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(kern, dim3((unsigned)n), dim3(64), lds, stream, a);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && !per_cell) {

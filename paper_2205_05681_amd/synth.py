@@ -419,7 +419,26 @@ def mech_large(seed=104):
                               must_have=CH4_MUST)
 
 
-MECHS = {"small": mech_small, "ch4": mech_ch4, "large": mech_large}
+def mech_n30(seed=106):
+    """30 species (C, H, O, N; at most C2), 180 reactions: 16 third-body, 12 Troe."""
+    return generate_mechanism(30, 180, 16, 12, True, ["C", "H", "O", "N"], 2, seed,
+                              must_have=CH4_MUST)
+
+
+def mech_n45(seed=107):
+    """45 species (C, H, O, N; at most C3), 260 reactions: 24 third-body, 18 Troe."""
+    return generate_mechanism(45, 260, 24, 18, True, ["C", "H", "O", "N"], 3, seed,
+                              must_have=CH4_MUST)
+
+
+def mech_n62(seed=108):
+    """62 species (C, H, O, N; at most C3), 380 reactions: 34 third-body, 28 Troe."""
+    return generate_mechanism(62, 380, 34, 28, True, ["C", "H", "O", "N"], 3, seed,
+                              must_have=CH4_MUST)
+
+
+MECHS = {"small": mech_small, "ch4": mech_ch4, "large": mech_large,
+         "n30": mech_n30, "n45": mech_n45, "n62": mech_n62}
 
 
 def mechanism_file(name, directory):

@@ -272,6 +272,45 @@ def test_batching_full_size_sampled(chem, ch4):
     assert ng[kind == 0].mean() < 5 and ng[kind == 1].mean() > 50
 
 
+@pytest.mark.parametrize("name", ["n30", "n45", "n62"])
+def test_mechanism_sizes_team_parity(chem, mech_dir, name):
+    """Mechanisms of 30, 45 and 62 species (state sizes 31, 46, 63: the
+    one-wavefront-per-cell kernels compiled for 32, 48 and 64 rows), 300
+    mixing-layer cells, dt = 1e-6 s, both one-wavefront-per-cell launches, and
+    the discrete adjoint of 8 cells against the oracle's tangent."""
+    import oracle
+    path, m = synth.mechanism_file(name, mech_dir)
+    o = oracle.Oracle(path)
+    say("case: %s mechanism (%d species), 300 cells" % (name, m.n_species))
+    T, P, Y = synth.states_mixing(m, 300, 209)
+    mech = chem.Mechanism(path)
+    r = o.integrate(T, P, Y, 1e-6)
+    assert np.all(r["status"] == 0)
+    for mode in ("team", "team_persistent"):
+        Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
+        assert np.all(sg == 0)
+        assert_parity(Tg, Yg, r["T"], r["Y"], name + " " + mode, o, (T, P, Y), 1e-6, max_frac=0.05)
+        assert_steps_parity(ng, r["n_acc"], o, (T, P, Y), 1e-6, max_frac=0.05)
+    # adjoint: per-cell gradient of T_final along a random ln A direction
+    idx = np.r_[np.argsort(-T)[:4], np.arange(4)]
+    Ts, Ps, Ys = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+    T1, Y1, h1, ns, st, ck = chem.integrate(mech, dev(Ts), dev(Ps), dev(Ys), 1e-6, checkpoint=True)
+    gT = torch.ones(idx.size, dtype=torch.float64, device="cuda")
+    gY = torch.zeros((m.n_species, idx.size), dtype=torch.float64, device="cuda")
+    g, _, _ = chem.adjoint(mech, ck, gT, gY, per_cell=True, initial=False)
+    torch.cuda.synchronize()
+    off, rec = ck.export()
+    ck.close()
+    mech.close()
+    g = g.cpu().numpy()
+    rng = np.random.default_rng(13)
+    for c in range(idx.size):
+        hs = rec[off[c]:off[c + 1] - 1, -1].copy()
+        v = rng.normal(size=len(m.reactions))
+        dT, dY = o.tangent(Ts[c], Ps[c], Ys[:, c], hs, v_lnA=v)
+        assert g[:, c] @ v == pytest.approx(dT, rel=1e-6, abs=1e-9 * np.abs(g[:, c]).sum() + 1e-300), c
+
+
 def test_large_full_size_sampled(chem, large):
     """The 111-species mechanism at its full size, 262,144 mixing-layer cells
     (dt = 1e-5 s), in the default launch (one cell per thread, N > 64); 64
