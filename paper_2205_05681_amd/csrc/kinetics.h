@@ -2,7 +2,10 @@
 // cell per thread.  Per-cell vectors live in a structure-of-arrays workspace
 // (element i of a cell at p[i * ld], consecutive cells adjacent), so every
 // access of a wavefront is one coalesced transaction; the mechanism tables are
-// read at wavefront-uniform indices and so go through scalar loads.
+// read at wavefront-uniform indices and so go through scalar loads.  The rate
+// law of one reaction (reaction_rate, templated on the scalar type for the
+// dual numbers of the adjoint) is shared with the one-wavefront-per-cell
+// kernels, which give each lane its own reaction.
 //
 // State (paper Sec. 2.1, eq. (state_vec)): Phi = (T, V, n_0 .. n_{K-2}) per
 // unit mass; the bath gas K-1 is closed by the ideal-gas law (eq. (n_nsp)).

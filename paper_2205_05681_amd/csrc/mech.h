@@ -14,9 +14,14 @@ constexpr int MAX_SIDE = 3;         // species per reaction side
 
 enum RxnType : int32_t { RX_ELEM = 0, RX_THIRD = 1, RX_LIND = 2, RX_TROE = 3 };
 
-// Device view of a mechanism.  All arrays are device pointers, structure of
-// arrays over reactions so that a wavefront walking reactions in lockstep reads
-// each field with one scalar load.
+// Device view of a mechanism.  All arrays are device pointers into one blob
+// (each array 256-byte aligned and followed by at least 256 zero bytes, so a
+// read just past an array's end stays in the blob).
+// A reaction's fields sit in a few per-reaction records (info, species,
+// coefficients, Arrhenius).  The one-cell-per-thread kernel reads them at a
+// wavefront-uniform reaction index (scalar loads); the one-wavefront-per-cell
+// kernels put one reaction on each lane, so neighbouring lanes read
+// neighbouring records.
 struct MechView {
   int32_t K, Nr, N;          // species, reactions, state size K + 1
   const double* W;           // [K]

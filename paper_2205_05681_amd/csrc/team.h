@@ -97,14 +97,14 @@ struct TeamLdsT {
   S* vec;    // [64]       staging of a lane-distributed vector
   int* plane;            // [64]
   // Two layouts.  bind(): dwdT and dwdV first, then the matrix, brow and the
-  // other vectors.  bind2(): the matrix at Jb and every vector at Vb (the
-  // adjoint's two matrix views share one vector block).
-  // elements of S after the matrix: brow and the vectors
+  // other vectors, one block of doubles(N) doubles whose last 32 hold plane.
+  // bind2(): the matrix at Jb and brow plus every vector at Vb (the adjoint's
+  // two matrix views share one vector block).
+  // Elements of S besides the matrix: brow and ten 64-entry vectors.
   static __host__ __device__ size_t vec_elems(int N) { return (size_t)(N + 1) + 10 * 64; }
   static __host__ __device__ size_t doubles(int N) {
     return ((size_t)N * (N + 1) + vec_elems(N)) * (sizeof(S) / sizeof(double)) + 32;
   }
-  // matrix at Jb, vectors at Vb (separately placed for the adjoint's two views)
   __device__ void bind2(S* Jb, S* Vb, int* pl, int N) {
     J = Jb;
     brow = Vb;
