@@ -495,11 +495,17 @@ __device__ __forceinline__ int team_lu(double* __restrict__ F, int ldj, int N, d
                                        double& rdiag) {
   const int lane = threadIdx.x;
   const bool own = lane < N;
+  const double* row = F + (own ? lane : 0) * ldj;
+  const int jn = own ? N : 0;   // entries of M in this lane's row
   double A[NMAX];
 #pragma unroll
   for (int j = 0; j < NMAX; ++j) {
-    const double m = (own && j < N) ? (j == lane ? d : 0.0) - F[lane * ldj + j] : 0.0;
-    A[j] = (!own && lane < NMAX && j == lane) ? 1.0 : m;
+    // the load is in this work-group's LDS for every j < NMAX; a select on the
+    // loaded value itself, without short-circuit terms, keeps the loads
+    // unconditional and issued back to back
+    const double f = (j < jn) ? row[j] : 0.0;
+    const double dj = ((j == lane) & (j < jn)) ? d : 0.0;
+    A[j] = ((lane >= N) & (j == lane)) ? 1.0 : dj - f;
   }
   int ord = lane < NMAX ? -1 : NMAX;          // pivot position of this lane's row; -1 while unused
   double rp_own = 0.0;                        // 1 / (this row's pivot)
@@ -533,6 +539,10 @@ __device__ __forceinline__ double team_solve(const double* __restrict__ F, int l
   const int lane = threadIdx.x;
   const bool own = lane < N;
   const double* row = F + (own ? lane : 0) * ldj;
+  // Masks without short-circuit conditions: a select whose condition contains
+  // own && ... becomes a branch around the LDS load, one full LDS round trip
+  // per entry.  Rows past N take lim = 0 (no entry of L).
+  const int lim = own ? lane : 0;
   b = gather(b, perm);                       // P b
   // forward: L y = P b (unit lower triangle)
 #pragma unroll
@@ -542,7 +552,7 @@ __device__ __forceinline__ double team_solve(const double* __restrict__ F, int l
     for (int t = 0; t < 8; ++t) {
       const int k = k0 + t;
       const double v = row[k];   // in this work-group's LDS for every k < NMAX; masked by a select
-      l[t] = (own && k < lane) ? v : 0.0;
+      l[t] = (k < lim) ? v : 0.0;
     }
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -559,7 +569,7 @@ __device__ __forceinline__ double team_solve(const double* __restrict__ F, int l
       const int k = k1 - t;
       const int kk = k >= 0 ? k : 0;
       const double v = row[kk] * bcast(rdiag, kk);
-      u[t] = (own && k > lane && k < N) ? v : 0.0;
+      u[t] = ((k > lane) & (k < N)) ? v : 0.0;   // lane < k < N: an own row
     }
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
