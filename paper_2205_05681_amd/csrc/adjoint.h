@@ -30,47 +30,108 @@
 namespace chem {
 
 // Solve M^T x = b with the factors of team_lu (P M = L U, perm, 1/U_ii) and
-// invperm, the inverse of perm.  b, x lane-distributed.
+// invperm, the inverse of perm.  b, x lane-distributed (lanes >= N hold 0 and
+// keep it).  As in team_solve, every column step is unrolled over NMAX >= N
+// (the steps past N change nothing), rows are read eight at a time (row k of
+// the factors, element `lane`, for every k < NMAX lies in this work-group's
+// LDS) and masked by selects on the loaded values.
+template <int NMAX>
 __device__ __forceinline__ double team_solve_t(const double* __restrict__ F, int ldj, int N,
                                                int invperm, double rdiag, double b) {
   const int lane = threadIdx.x;
+  const double* col = F + lane;
   // U^T z = b (lower triangular): column k of U^T is row k of U
-  for (int k = 0; k < N; ++k) {
-    const double zk = bcast(b, k) * bcast(rdiag, k);
-    if (lane == k) b = zk;
-    if (lane > k && lane < N) b -= F[k * ldj + lane] * zk;
+#pragma unroll
+  for (int k0 = 0; k0 < NMAX; k0 += 8) {
+    double u[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + t;
+      const double v = col[k * ldj];
+      u[t] = ((lane > k) & (lane < N)) ? v : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k0 + t;
+      const double zk = (k < N) ? bcast(b, k) * bcast(rdiag, k) : 0.0;
+      const double nb = b - u[t] * zk;
+      b = ((lane == k) & (k < N)) ? zk : nb;
+    }
   }
   // L^T w = z (unit upper triangular)
-  for (int k = N - 1; k >= 1; --k) {
-    const double wk = bcast(b, k);
-    if (lane < k) b -= F[k * ldj + lane] * wk;
+#pragma unroll
+  for (int k1 = NMAX - 1; k1 >= 1; k1 -= 8) {
+    double l[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k1 - t;
+      const double v = col[(k >= 0 ? k : 0) * ldj];
+      l[t] = ((lane < k) & (k < N)) ? v : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int k = k1 - t;
+      if (k >= 1) {
+        const double wk = (k < N) ? bcast(b, k) : 0.0;
+        b -= l[t] * wk;
+      }
+    }
   }
   // x = P^T w
   return gather(b, invperm);
 }
 
-// (J^T mu)_c for the Jacobian held in LDS (lanes over columns).
+// (J^T mu)_c for the Jacobian held in LDS (lanes over columns); rows are read
+// eight at a time (a loop over blocks of eight rows up to NMAX >= N, with the
+// rows past N masked), so that eight loads are in flight at once.
+template <int NMAX>
 __device__ __forceinline__ double team_jt_mu(const double* __restrict__ J, int ldj, int N, double mu) {
   const int lane = threadIdx.x;
+  const double* col = J + lane;
   double acc = 0.0;
-  for (int r = 0; r < N; ++r) {
-    const double m = bcast(mu, r);
-    if (lane < N) acc += J[r * ldj + lane] * m;
+#pragma unroll 1
+  for (int r0 = 0; r0 < NMAX; r0 += 8) {
+    double e[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = r0 + t;
+      const double v = col[r * ldj];
+      e[t] = ((lane < N) & (r < N)) ? v : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = r0 + t;
+      const double m = (r < N) ? bcast(mu, r) : 0.0;
+      acc += e[t] * m;
+    }
   }
   return acc;
 }
 
 // (dJ^T mu)_c and (J^T mu)_c for a dual Jacobian (value and directional derivative).
+template <int NMAX>
 __device__ __forceinline__ void team_jt_mu_dual(const Dd* __restrict__ J, int ldj, int N, double mu,
                                                 double& val_part, double& der_part) {
   const int lane = threadIdx.x;
+  const Dd* col = J + lane;
   double a = 0.0, b = 0.0;
-  for (int r = 0; r < N; ++r) {
-    const double m = bcast(mu, r);
-    if (lane < N) {
-      const Dd e = J[r * ldj + lane];
-      a += e.v * m;
-      b += e.d * m;
+#pragma unroll 1
+  for (int r0 = 0; r0 < NMAX; r0 += 8) {
+    double ev[8], ed[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = r0 + t;
+      const Dd e = col[r * ldj];
+      const bool on = (lane < N) & (r < N);
+      ev[t] = on ? e.v : 0.0;
+      ed[t] = on ? e.d : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = r0 + t;
+      const double m = (r < N) ? bcast(mu, r) : 0.0;
+      a += ev[t] * m;
+      b += ed[t] * m;
     }
   }
   val_part = a;

@@ -564,29 +564,29 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
     double phib = lam;
     double ub1 = ROS4_M1 * lam, ub2 = ROS4_M2 * lam, ub3 = ROS4_M3 * lam;
     const double ub4 = ROS4_M4 * lam;
-    const double mu4 = team_solve_t(F, ldj, N, invperm, rdiag, ub4);
+    const double mu4 = team_solve_t<NMAX>(F, ldj, N, invperm, rdiag, ub4);
     double F3b = mu4;
     ub1 += ROS4_C41 * ih * mu4;
     ub2 += ROS4_C42 * ih * mu4;
     ub3 += ROS4_C43 * ih * mu4;
-    const double mu3 = team_solve_t(F, ldj, N, invperm, rdiag, ub3);
+    const double mu3 = team_solve_t<NMAX>(F, ldj, N, invperm, rdiag, ub3);
     F3b += mu3;
     ub1 += ROS4_C31 * ih * mu3;
     ub2 += ROS4_C32 * ih * mu3;
     team_rhs_jac<double>(M, P, y3, LB, a.lnA);
-    const double y3b = team_jt_mu(LB.J, ldj, N, F3b);
+    const double y3b = team_jt_mu<NMAX>(LB.J, ldj, N, F3b);
     team_pbar<double>(M, P, y3, F3b, LB, a.lnA, pbar, true);
     phib += y3b;
     ub1 += ROS4_A31 * y3b;
     ub2 += ROS4_A32 * y3b;
-    const double mu2 = team_solve_t(F, ldj, N, invperm, rdiag, ub2);
+    const double mu2 = team_solve_t<NMAX>(F, ldj, N, invperm, rdiag, ub2);
     ub1 += ROS4_C21 * ih * mu2;
     team_rhs_jac<double>(M, P, y2, LB, a.lnA);
-    const double y2b = team_jt_mu(LB.J, ldj, N, mu2);
+    const double y2b = team_jt_mu<NMAX>(LB.J, ldj, N, mu2);
     team_pbar<double>(M, P, y2, mu2, LB, a.lnA, pbar, true);
     phib += y2b;
     ub1 += ROS4_A21 * y2b;
-    const double mu1 = team_solve_t(F, ldj, N, invperm, rdiag, ub1);
+    const double mu1 = team_solve_t<NMAX>(F, ldj, N, invperm, rdiag, ub1);
     wsync();
     // ---- J(Phi)^T mu1 and the terms through M(Phi): dual evaluations along u_i
 #pragma unroll 1
@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
       const double mui = (i == 0) ? mu1 : (i == 1) ? mu2 : (i == 2) ? mu3 : mu4;
       team_rhs_jac<Dd>(M, P, Dd{x, (lane < N) ? ui : 0.0}, LD, a.lnA);
       double vpart, dpart;
-      team_jt_mu_dual(LD.J, ldj, N, mui, vpart, dpart);
+      team_jt_mu_dual<NMAX>(LD.J, ldj, N, mui, vpart, dpart);
       phib += dpart;
       if (i == 0) phib += vpart;
       team_pbar<Dd>(M, P, Dd{x, (lane < N) ? ui : 0.0}, mui, LD, a.lnA, pbar, i == 0);
