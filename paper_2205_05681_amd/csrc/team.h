@@ -38,12 +38,12 @@ __device__ __forceinline__ double gather(double v, int src) { return __shfl(v, s
 
 // Cross-lane move inside 16-lane rows (DPP); CTRL is the DPP control word.
 // The controls used here permute lanes inside a row, so every lane has a
-// source and the "old" operand (the value itself) is never taken.
+// source (the bound-control setting never applies).  A move without an "old"
+// operand lets the compiler fold it into the consuming ALU instruction.
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
-  const int l = __double2loint(v), h = __double2hiint(v);
-  const int lo = __builtin_amdgcn_update_dpp(l, l, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(h, h, CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 constexpr int DPP_QUAD_1032 = 0xB1;   // quad_perm [1,0,3,2]
@@ -419,11 +419,12 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
 }
 
 // Largest of a non-negative 32-bit key over the 64 lanes (DPP inside rows,
-// then the four rows by v_readlane).
+// each step one v_max_u32 with a DPP source, then the four rows by
+// v_readlane).
 __device__ __forceinline__ unsigned umax32(unsigned a, unsigned b) { return a > b ? a : b; }
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp32(unsigned v) {
-  return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false);
+  return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   v = umax32(v, dpp32<DPP_QUAD_1032>(v));
@@ -471,7 +472,9 @@ __device__ __forceinline__ void team_lu_col(double (&A)[NMAX], int& ord, double&
     A[KC] = upd ? l : A[KC];
     ord = is_p ? KC : ord;
     rp_own = is_p ? rp : rp_own;
-    pv = (lane == KC) ? p : pv;
+    // lane KC records p (a v_writelane with a constant lane: no per-column
+    // lane mask to keep live)
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(pv) : "s"(p), "i"(KC));
 #pragma unroll
     for (int j = KC + 1; j < NMAX; ++j) A[j] -= l * bcast(A[j], p);
     team_lu_col<NMAX, KC + 1>(A, ord, rp_own, pv, rc);
