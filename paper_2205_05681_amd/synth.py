@@ -437,8 +437,32 @@ def mech_n62(seed=108):
                               must_have=CH4_MUST)
 
 
+def mech_n15(seed=109):
+    """15 species (C, H, O, N; C1 only), 60 reactions: 6 third-body, 4 Troe
+    (state size 16: exactly the rows of the smallest one-wavefront-per-cell
+    kernel)."""
+    return generate_mechanism(15, 60, 6, 4, True, ["C", "H", "O", "N"], 1, seed,
+                              must_have=("H2", "H", "O", "O2", "OH", "H2O", "HO2", "CH3", "CH4",
+                                         "CO", "CO2", "CHO"))
+
+
+def mech_n55(seed=110):
+    """55 species (C, H, O, N; at most C3), 330 reactions: 30 third-body, 24 Troe
+    (state size 56: exactly the rows of the 56-row kernel)."""
+    return generate_mechanism(55, 330, 30, 24, True, ["C", "H", "O", "N"], 3, seed,
+                              must_have=CH4_MUST)
+
+
+def mech_n63(seed=111):
+    """63 species (C, H, O, N; at most C3), 385 reactions: 34 third-body, 28 Troe
+    (state size 64: one row per lane of the wavefront)."""
+    return generate_mechanism(63, 385, 34, 28, True, ["C", "H", "O", "N"], 3, seed,
+                              must_have=CH4_MUST)
+
+
 MECHS = {"small": mech_small, "ch4": mech_ch4, "large": mech_large,
-         "n30": mech_n30, "n45": mech_n45, "n62": mech_n62}
+         "n15": mech_n15, "n30": mech_n30, "n45": mech_n45, "n55": mech_n55,
+         "n62": mech_n62, "n63": mech_n63}
 
 
 def mechanism_file(name, directory):

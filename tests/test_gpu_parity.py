@@ -272,12 +272,14 @@ def test_batching_full_size_sampled(chem, ch4):
     assert ng[kind == 0].mean() < 5 and ng[kind == 1].mean() > 50
 
 
-@pytest.mark.parametrize("name", ["n30", "n45", "n62"])
+@pytest.mark.parametrize("name", ["n15", "n30", "n45", "n55", "n62", "n63"])
 def test_mechanism_sizes_team_parity(chem, mech_dir, name):
-    """Mechanisms of 30, 45 and 62 species (state sizes 31, 46, 63: the
-    one-wavefront-per-cell kernels compiled for 32, 48 and 64 rows), 300
-    mixing-layer cells, dt = 1e-6 s, both one-wavefront-per-cell launches, and
-    the discrete adjoint of 8 cells against the oracle's tangent."""
+    """Mechanisms of 15, 30, 45, 55, 62 and 63 species (state sizes 16, 31,
+    46, 56, 63, 64: the one-wavefront-per-cell kernels compiled for 16, 32,
+    48, 56 and 64 rows, with and without identity padding rows, up to one row
+    per lane), 300 mixing-layer cells, dt = 1e-6 s, both one-wavefront-per-cell
+    launches, and the discrete adjoint of 8 cells against the oracle's
+    tangent."""
     import oracle
     path, m = synth.mechanism_file(name, mech_dir)
     o = oracle.Oracle(path)
