@@ -182,7 +182,7 @@ def main():
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported "
-              "(cells are independent, see the sharding notes)" % a.gpus, file=sys.stderr)
+              "(cells are independent: several GPUs would each take a contiguous share of the batch)" % a.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
