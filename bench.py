@@ -181,7 +181,7 @@ def main():
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported "
+        print("bench.py measures one GPU; --gpus %d is not supported "
               "(cells are independent: several GPUs would each take a contiguous share of the batch)" % a.gpus, file=sys.stderr)
         sys.exit(2)
 
