@@ -15,30 +15,46 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.cpp")
+# The same source built with fused multiply-adds contracted: a rounding-level
+# variant of the oracle (the kind of difference a GPU build has), used by the
+# parity tests to measure how far rounding alone moves each cell.
+LIB_FMA = os.path.join(HERE, "liboracle_fma.so")
+FMA_FLAGS = ("-mfma", "-ffp-contract=fast")
 
 _d = C.POINTER(C.c_double)
 _i = C.POINTER(C.c_int32)
 
 
-def build(force=True):
-    """Compile the oracle with g++ (OpenMP over cells)."""
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC", SRC, "-o", tmp])
-    os.replace(tmp, LIB)
-    return LIB
+FLAGS = ["-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC"]
+
+
+def build_all(force=True):
+    """The oracle and its FMA-contracted variant."""
+    build(force)
+    build(force, out=LIB_FMA, flags=FMA_FLAGS)
+
+
+def build(force=True, src=SRC, out=LIB, flags=()):
+    """Compile the oracle with g++ (OpenMP over cells).  src/out/flags let a
+    test build a variant (other floating-point flags, or a planted mistake)."""
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++", *FLAGS, *flags, src, "-o", tmp])
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None
 
 
-def lib():
+def lib(path=None):
+    """The oracle library (built on first use), or the one at ``path``."""
     global _lib
-    if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if path is not None or _lib is None:
+        if path is None and (not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path or LIB)
         L.or_mech_load.restype = C.c_void_p
         L.or_mech_load.argtypes = [C.c_char_p]
         L.or_mech_free.argtypes = [C.c_void_p]
@@ -49,20 +65,26 @@ def lib():
         L.or_rhs.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
         L.or_jacobian.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
         L.or_lu_solve.argtypes = [C.c_int, _d, _d, _d]
-        L.or_ros4_table.argtypes = [_d]
-        L.or_step.argtypes = [C.c_void_p, C.c_double, _d, C.c_double, _d, _d]
+        L.or_method_table.argtypes = [C.c_int, _d]
+        L.or_step.argtypes = [C.c_void_p, C.c_double, _d, C.c_double, _d, _d, C.c_int, C.c_int]
         L.or_to_phi.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d]
         L.or_from_phi.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
         L.or_integrate.restype = C.c_int
         L.or_integrate.argtypes = [C.c_void_p, C.c_int64, _d, _d, _d, C.c_int64, C.c_double, C.c_double,
-                                   C.c_double, _d, _d, _d, _i, _i, _i, _d, C.c_int, C.c_int]
+                                   C.c_double, _d, _d, _d, _i, _i, _i, _d, C.c_int, C.c_int, C.c_int,
+                                   C.c_int]
         L.or_record_steps.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, C.c_double, C.c_double,
-                                      C.c_double, C.c_double, _d, _d, C.c_int, _d, _d]
-        L.or_replay.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d, _d, C.c_int, _d, _d]
+                                      C.c_double, C.c_double, _d, _d, C.c_int, _d, _d, C.c_int, C.c_int]
+        L.or_replay.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d, _d, C.c_int, _d, _d, C.c_int]
         L.or_tangent.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d, _d, C.c_int, _d,
-                                 C.c_double, _d, _d, _d]
-        L.or_integrate_linear.argtypes = [C.c_int, _d, _d, C.c_double, C.c_double, C.c_double, C.c_double]
-        L.or_integrate_riccati.argtypes = [_d, C.c_double, C.c_double, C.c_double, C.c_double]
+                                 C.c_double, _d, _d, _d, C.c_int]
+        L.or_integrate_linear.argtypes = [C.c_int, _d, _d, C.c_double, C.c_double, C.c_double, C.c_double,
+                                          C.c_int, C.c_int]
+        L.or_linear_step.argtypes = [C.c_int, _d, _d, C.c_double, _d, _d, C.c_int, C.c_int]
+        L.or_integrate_cubic.argtypes = [_d, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                           C.c_int]
+        if path is not None:
+            return L
         _lib = L
     return _lib
 
@@ -85,12 +107,25 @@ def _f64(a):
 R_U = 8314.462618
 P_ATM = 101325.0
 
+# Rosenbrock solvers of the paper's solver table and the error estimators
+METHODS = {"ros4": 0, "ros3": 1, "rodas3": 2, "rodas4": 3}
+ESTIMATORS = {"embedded": 0, "filtered": 1}
+
+
+def _mid(method):
+    return METHODS[method] if isinstance(method, str) else int(method)
+
+
+def _eid(estimator):
+    return ESTIMATORS[estimator] if isinstance(estimator, str) else int(estimator)
+
 
 class Oracle:
     """One parsed mechanism in the oracle."""
 
-    def __init__(self, path):
-        self.L = lib()
+    def __init__(self, path, library=None):
+        self.L = library if library is not None else lib()
+        self.path = path
         self.h = self.L.or_mech_load(path.encode())
         if not self.h:
             raise ValueError("oracle could not parse %s" % path)
@@ -132,9 +167,10 @@ class Oracle:
         self.L.or_jacobian(self.h, float(P), _p(_f64(phi)), _p(_f64(lnA)), _p(J))
         return J
 
-    def step(self, P, phi, h):
+    def step(self, P, phi, h, method="ros4", estimator="embedded"):
         out, err = np.zeros(self.N), np.zeros(self.N)
-        rc = self.L.or_step(self.h, float(P), _p(_f64(phi)), float(h), _p(out), _p(err))
+        rc = self.L.or_step(self.h, float(P), _p(_f64(phi)), float(h), _p(out), _p(err), _mid(method),
+                            _eid(estimator))
         return rc, out, err
 
     def to_phi(self, T, P, Y):
@@ -150,7 +186,7 @@ class Oracle:
 
     # -- batched integration ---------------------------------------------------
     def integrate(self, T, P, Y, dt, rtol=1e-6, atol=1e-10, h=None, lnA=None, max_steps=0,
-                  nthreads=0):
+                  nthreads=0, method="ros4", estimator="embedded"):
         """Y is (K, n).  Returns dict with T, Y, h, n_acc, n_rej, status, threads."""
         T = _f64(T)
         P = _f64(P)
@@ -163,43 +199,51 @@ class Oracle:
         na, nr, st = (np.zeros(n, np.int32) for _ in range(3))
         thr = self.L.or_integrate(self.h, n, _p(T), _p(P), _p(Y), n, float(dt), float(rtol), float(atol),
                                   _p(hio), _p(Tout), _p(Yout), _p(na), _p(nr), _p(st), _p(_f64(lnA)),
-                                  int(max_steps), int(nthreads))
+                                  int(max_steps), int(nthreads), _mid(method), _eid(estimator))
+        if thr < 0:
+            raise ValueError("unknown method")
         return dict(T=Tout, Y=Yout, h=hio, n_acc=na, n_rej=nr, status=st, threads=thr)
 
-    def record_steps(self, T, P, Y, dt, rtol=1e-6, atol=1e-10, h0=0.0, lnA=None, cap=1000000):
+    def record_steps(self, T, P, Y, dt, rtol=1e-6, atol=1e-10, h0=0.0, lnA=None, cap=1000000,
+                     method="ros4", estimator="embedded"):
         hs = np.zeros(cap)
         To = np.zeros(1)
         Yo = np.zeros(self.K)
         n = self.L.or_record_steps(self.h, float(T), float(P), _p(_f64(Y)), float(dt), float(rtol),
-                                   float(atol), float(h0), _p(_f64(lnA)), _p(hs), cap, _p(To), _p(Yo))
+                                   float(atol), float(h0), _p(_f64(lnA)), _p(hs), cap, _p(To), _p(Yo),
+                                   _mid(method), _eid(estimator))
         if n < 0:
             raise RuntimeError("oracle integration failed with status %d" % -n)
         return hs[:n].copy(), To[0], Yo
 
-    def replay(self, T, P, Y, hs, lnA=None):
+    def replay(self, T, P, Y, hs, lnA=None, method="ros4"):
         To = np.zeros(1)
         Yo = np.zeros(self.K)
         hs = _f64(hs)
         rc = self.L.or_replay(self.h, float(T), float(P), _p(_f64(Y)), _p(_f64(lnA)), _p(hs), hs.size,
-                              _p(To), _p(Yo))
+                              _p(To), _p(Yo), _mid(method))
         if rc:
             raise RuntimeError("replay failed")
         return To[0], Yo
 
-    def tangent(self, T, P, Y, hs, v_lnA=None, dT0=0.0, dY0=None, lnA=None):
+    def tangent(self, T, P, Y, hs, v_lnA=None, dT0=0.0, dY0=None, lnA=None, method="ros4"):
         dT = np.zeros(1)
         dY = np.zeros(self.K)
         hs = _f64(hs)
         self.L.or_tangent(self.h, float(T), float(P), _p(_f64(Y)), _p(_f64(lnA)), _p(hs), hs.size,
-                          _p(_f64(v_lnA)), float(dT0), _p(_f64(dY0)), _p(dT), _p(dY))
+                          _p(_f64(v_lnA)), float(dT0), _p(_f64(dY0)), _p(dT), _p(dY), _mid(method))
         return dT[0], dY
 
 
-def ros4_table():
-    t = np.zeros(18)
-    lib().or_ros4_table(_p(t))
-    names = "gamma a21 a31 a32 c21 c31 c32 c41 c42 c43 m1 m2 m3 m4 e1 e2 e3 e4".split()
-    return dict(zip(names, t))
+def method_table(method="ros4"):
+    """The transformed coefficients of a method: dict with s, gamma, elo and the
+    arrays a (s, s), c (s, s), m (s,), e (s,)."""
+    t = np.zeros(87)
+    if lib().or_method_table(_mid(method), _p(t)):
+        raise ValueError(method)
+    s = int(t[0])
+    return dict(s=s, gamma=t[1], elo=t[2], a=t[3:39].reshape(6, 6)[:s, :s].copy(),
+                c=t[39:75].reshape(6, 6)[:s, :s].copy(), m=t[75:75 + s].copy(), e=t[81:81 + s].copy())
 
 
 def lu_solve(A, b):
@@ -212,14 +256,28 @@ def lu_solve(A, b):
     return x
 
 
-def integrate_linear(A, y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0):
+def integrate_linear(A, y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0, method="ros4", estimator="embedded"):
     A = _f64(A)
     y = _f64(y0).copy()
-    n = lib().or_integrate_linear(y.size, _p(A), _p(y), float(dt), float(rtol), float(atol), float(h_fixed))
+    n = lib().or_integrate_linear(y.size, _p(A), _p(y), float(dt), float(rtol), float(atol), float(h_fixed),
+                                  _mid(method), _eid(estimator))
     return y, n
 
 
-def integrate_riccati(y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0):
+def linear_step(A, y0, h, method="ros4", estimator="embedded"):
+    """One step of y' = A y: (y_new, error estimate)."""
+    A = _f64(A)
+    y = _f64(y0)
+    out, err = np.zeros_like(y), np.zeros_like(y)
+    rc = lib().or_linear_step(y.size, _p(A), _p(y), float(h), _p(out), _p(err), _mid(method), _eid(estimator))
+    if rc:
+        raise np.linalg.LinAlgError("step failed")
+    return out, err
+
+
+def integrate_cubic(y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0, method="ros4", estimator="embedded"):
+    """y' = -y^3 from y0 over [0, dt]."""
     y = np.array([float(y0)])
-    n = lib().or_integrate_riccati(_p(y), float(dt), float(rtol), float(atol), float(h_fixed))
+    n = lib().or_integrate_cubic(_p(y), float(dt), float(rtol), float(atol), float(h_fixed), _mid(method),
+                                   _eid(estimator))
     return y[0], n

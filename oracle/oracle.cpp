@@ -1,9 +1,10 @@
-// CPU FP64 oracle for batched constant-pressure chemistry integration with ROS4.
+// CPU FP64 oracle for batched constant-pressure chemistry integration with the
+// linearly implicit Rosenbrock solvers ROS4 (the default), ROS3, RODAS3, RODAS4.
 //
 // TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
 // includes this file; only the tests, the smoke check and the CPU-baseline leg
 // of the benchmark load it.  It shares no code with the HIP path: it has its
-// own mechanism parser, its own thermochemistry, its own ROS4 table literals.
+// own mechanism parser, its own thermochemistry, its own method tables.
 //
 // It is deliberately plain and slow: one cell at a time, textbook loops, no
 // blocking or fusion; OpenMP runs independent cells on separate threads.
@@ -20,8 +21,8 @@
 //     the definition literally: forward-mode dual numbers differentiate f, one
 //     column per pass (exact to rounding, no truncation error);
 //   * the transformed Rosenbrock scheme (Sec. 2.3, eq. (ros) and the
-//     u_i / a_ij / c_ij / m_j form that follows it), 4 stages, one LU per step;
-//     ROS4 with an L-stable 4(3) coefficient set (Table T:solvers);
+//     u_i / a_ij / c_ij / m_j form that follows it), one LU per step, with the
+//     coefficient sets of the solvers in Table T:solvers;
 //   * adaptive step control from rtol/atol (Sec. 3.1), with the returned last
 //     internal step reused as the next call's first step (Sec. 2.4.1);
 //   * conversion (T, P, Y) <-> Phi through [C_i] = rho Y_i / W_i = n_i / V
@@ -312,31 +313,80 @@ void lu_solve(int n, const S* LU, const int* piv, S* b) {
   }
 }
 
-// ---------------------------------------------------------------- ROS4 table
-// An L-stable 4-stage order-4 Rosenbrock method with an embedded order-3
-// solution, in the transformed form u_i = sum_j gamma_ij k_j (Sec. 2.3).
-// gamma = 1/x2, x2 the second root of the Laguerre polynomial L4, gives
-// R(inf) = 0; alpha_4j = alpha_3j so stage 4 reuses stage 3's f.  The free
-// parameters were fixed at alpha_21 = 2 gamma, alpha_3 = 0.45, b_4 = 0.4, and
-// the embedded weights have bhat_4 = 0.
-const double GAM = 0.57281606248213485541;
-const double A21 = 2.0;
-const double A31 = 1.491001215556513813960407;
-const double A32 = 0.2283940090236591778889569;
-const double C21 = -7.137649921358897064355991;
-const double C31 = -6.196702482993044766389505;
-const double C32 = -0.8558736500387530085234008;
-const double C41 = 5.964333552759764215600564;
-const double C42 = 0.4379266338878570570784905;
-const double C43 = 2.525577246716920611308754;
-const double M1 = 1.63885860954486232683164;
-const double M2 = 0.474955117534000084335749;
-const double M3 = -0.07416508734030706110427568;
-const double M4 = 0.6983044404633386302747267;
-const double E1 = 0.09734671529814985040858406;
-const double E2 = 0.2866125685892372986834792;
-const double E3 = 0.6849355088701844022099764;
-const double E4 = 0.6983044404633386302747267;
+// ---------------------------------------------------------------- Rosenbrock tables
+// The four linearly implicit solvers of the paper's solver table (Table
+// T:solvers), in the transformed form of Sec. 2.3: with u_i = sum_j gamma_ij k_j,
+//   (I/(h gamma) - J) u_i = f(y + sum_{j<i} a_ij u_j) + sum_{j<i} (c_ij / h) u_j,
+//   y_new = y + sum_j m_j u_j,   error estimate sum_j e_j u_j,
+// where a = alpha Gamma^-1, C = diag(1/gamma) - Gamma^-1, m = b Gamma^-1 and
+// e = (b - bhat) Gamma^-1 for the embedded weights bhat.  The coefficients are
+// the published ones of the references the table gives: ROS3 and RODAS3 from
+// Sandu et al. (1997), ROS4 (the L-stable set) and RODAS4 from Hairer and
+// Wanner's Solving ODEs II.  `elo` is the order of the error estimate's
+// leading term (embedded order + 1), the exponent of the step-size rule.
+struct Method {
+  const char* name;
+  int s;
+  double gamma;
+  double a[6][6], c[6][6], m[6], e[6];
+  double elo;
+};
+
+const Method ROS3 = {
+    "ros3", 3, 0.43586652150845899941601945119356,
+    {{0}, {1.0}, {1.0, 0.0}},
+    {{0}, {-1.0156171083877702091975600115545},
+     {4.0759956452537699824805835358067, 9.2076794298330791242156818474003}},
+    {1.0, 6.1697947043828245592553615689730, -0.42772256543218573326238373806514},
+    {0.5, -2.9079558716805469821718236208017, 0.22354069897811569627360909276199},
+    3.0};
+
+const Method ROS4 = {
+    "ros4", 4, 0.57282,
+    {{0}, {2.0}, {1.867943637803922, 0.2344449711399156},
+     {1.867943637803922, 0.2344449711399156, 0.0}},
+    {{0}, {-7.137615036412310}, {2.580708087951457, 0.6515950076447975},
+     {-2.137148994382534, -0.3214669691237626, -0.6949742501781779}},
+    {2.255570073418735, 0.2870493262186792, 0.4353179431840180, 1.093502252409163},
+    {-0.2815431932141155, -0.07276199124938920, -0.1082196201495311, -1.093502252409163},
+    4.0};
+
+const Method RODAS3 = {
+    "rodas3", 4, 0.5,
+    {{0}, {0.0}, {2.0, 0.0}, {2.0, 0.0, 1.0}},
+    {{0}, {4.0}, {1.0, -1.0}, {1.0, -1.0, -8.0 / 3.0}},
+    {2.0, 0.0, 1.0, 1.0},
+    {0.0, 0.0, 0.0, 1.0},
+    3.0};
+
+const Method RODAS4 = {
+    "rodas4", 6, 0.25,
+    {{0},
+     {1.544},
+     {0.9466785280815826, 0.2557011698983284},
+     {3.314825187068521, 2.896124015972201, 0.9986419139977817},
+     {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950},
+     {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0}},
+    {{0},
+     {-5.6688},
+     {-2.430093356833875, -0.2063599157091915},
+     {-0.1073529058151375, -9.594562251023355, -20.47028614809616},
+     {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.70890893206160},
+     {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136,
+      -6.058818238834054}},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0, 1.0},
+    {0.0, 0.0, 0.0, 0.0, 0.0, 1.0},
+    4.0};
+
+const Method* method_of(int id) {
+  switch (id) {
+    case 0: return &ROS4;
+    case 1: return &ROS3;
+    case 2: return &RODAS3;
+    case 3: return &RODAS4;
+    default: return nullptr;
+  }
+}
 
 // A system for the integrator: dimension, f and J at a state.
 struct ChemSys {
@@ -359,38 +409,64 @@ struct LinSys {            // y' = A y
   }
 };
 
-struct RiccatiSys {        // y' = -y^2
+struct CubicSys {          // y' = -y^3, y(t) = y0 / sqrt(1 + 2 y0^2 t)
   int n() const { return 1; }
-  template <class S> void f(const S* y, const S*, S* out) const { out[0] = -(y[0] * y[0]); }
-  template <class S> void jac(const S* y, const S*, S* J) const { J[0] = -2.0 * y[0]; }
+  template <class S> void f(const S* y, const S*, S* out) const { out[0] = -(y[0] * y[0] * y[0]); }
+  template <class S> void jac(const S* y, const S*, S* J) const { J[0] = -3.0 * (y[0] * y[0]); }
 };
 
-// One ROS4 step of size h from y.  Returns the LU's code (0 = success).
+// Error estimates.  EST_EMBEDDED is the method's own: sum_j e_j u_j, the
+// difference of the two solutions.  EST_FILTERED applies (I - h gamma J)^-1 to
+// it, the filter Shampine proposed and Hairer and Wanner use in RADAU5: it
+// keeps the leading h^elo term and takes the estimate of a strongly damped mode
+// to zero, where the embedded solution of a 4-stage method of order 4 cannot
+// damp it.
+enum { EST_EMBEDDED = 0, EST_FILTERED = 1 };
+
+// One step of size h from y with method `mt`.  Returns the LU's code (0 =
+// success).  Stages whose argument equals the previous stage's (row i of a
+// equal to row i-1) share that stage's f, as the methods are built for.
 template <class Sys, class S>
-int ros4_step(const Sys& sys, const S* y, const S* lnA, double h, S* ynew, S* err) {
-  const int n = sys.n();
-  std::vector<S> J(n * n), u1(n), u2(n), u3(n), u4(n), Yi(n), F(n), F3(n);
+int ros_step(const Sys& sys, const Method& mt, const S* y, const S* lnA, double h, int estimator,
+             S* ynew, S* err) {
+  const int n = sys.n(), s = mt.s;
+  std::vector<S> J(n * n), Yi(n), F(n);
+  std::vector<std::vector<S>> u(s, std::vector<S>(n));
   std::vector<int> piv(n);
   sys.jac(y, lnA, J.data());
   for (int i = 0; i < n * n; ++i) J[i] = -J[i];
-  for (int i = 0; i < n; ++i) J[i * n + i] += 1.0 / (h * GAM);
+  for (int i = 0; i < n; ++i) J[i * n + i] += 1.0 / (h * mt.gamma);
   int rc = lu(n, J.data(), piv.data());
   if (rc) return rc;
-  sys.f(y, lnA, u1.data());
-  lu_solve(n, J.data(), piv.data(), u1.data());
-  for (int i = 0; i < n; ++i) Yi[i] = y[i] + A21 * u1[i];
-  sys.f(Yi.data(), lnA, F.data());
-  for (int i = 0; i < n; ++i) u2[i] = F[i] + (C21 / h) * u1[i];
-  lu_solve(n, J.data(), piv.data(), u2.data());
-  for (int i = 0; i < n; ++i) Yi[i] = y[i] + A31 * u1[i] + A32 * u2[i];
-  sys.f(Yi.data(), lnA, F3.data());
-  for (int i = 0; i < n; ++i) u3[i] = F3[i] + (C31 * u1[i] + C32 * u2[i]) / h;
-  lu_solve(n, J.data(), piv.data(), u3.data());
-  for (int i = 0; i < n; ++i) u4[i] = F3[i] + (C41 * u1[i] + C42 * u2[i] + C43 * u3[i]) / h;
-  lu_solve(n, J.data(), piv.data(), u4.data());
-  for (int i = 0; i < n; ++i) {
-    ynew[i] = y[i] + M1 * u1[i] + M2 * u2[i] + M3 * u3[i] + M4 * u4[i];
-    err[i] = E1 * u1[i] + E2 * u2[i] + E3 * u3[i] + E4 * u4[i];
+  for (int i = 0; i < s; ++i) {
+    bool same = i > 0;
+    for (int j = 0; j < i && same; ++j) same = mt.a[i][j] == (j < i - 1 ? mt.a[i - 1][j] : 0.0);
+    if (!same) {
+      for (int k = 0; k < n; ++k) {
+        Yi[k] = y[k];
+        for (int j = 0; j < i; ++j) Yi[k] += mt.a[i][j] * u[j][k];
+      }
+      sys.f(Yi.data(), lnA, F.data());
+    }
+    for (int k = 0; k < n; ++k) {
+      S r = F[k];
+      for (int j = 0; j < i; ++j) r += (mt.c[i][j] / h) * u[j][k];
+      u[i][k] = r;
+    }
+    lu_solve(n, J.data(), piv.data(), u[i].data());
+  }
+  for (int k = 0; k < n; ++k) {
+    ynew[k] = y[k];
+    err[k] = C<S>(0.0);
+    for (int j = 0; j < s; ++j) {
+      ynew[k] += mt.m[j] * u[j][k];
+      err[k] += mt.e[j] * u[j][k];
+    }
+  }
+  if (estimator == EST_FILTERED) {
+    // (I - h gamma J)^-1 = M^-1 / (h gamma), M = I/(h gamma) - J factored above
+    lu_solve(n, J.data(), piv.data(), err);
+    for (int k = 0; k < n; ++k) err[k] = err[k] / (h * mt.gamma);
   }
   return 0;
 }
@@ -399,12 +475,15 @@ struct Ctl {
   double rtol, atol, h_min = 1e-20, safety = 0.9, fac_min = 0.2, fac_max = 6.0;
   int max_steps = 100000;
   int max_bad = 10;
+  const Method* mt = &ROS4;
+  int estimator = EST_EMBEDDED;
 };
 
 struct Outcome { int accepted = 0, rejected = 0, status = 0; double h_next = 0; };
 
-// Adaptive integration of y over [0, dt].  h0 <= 0 means h0 = dt.  Records the
-// accepted step sizes when ``hist`` is given.
+// Adaptive integration of y over [0, dt] (Sec. 3.1 tolerances; the constants
+// are the readings listed with the design notes).  h0 <= 0 means h0 = dt.
+// Records the accepted step sizes when ``hist`` is given.
 template <class Sys>
 Outcome integrate(const Sys& sys, double* y, double dt, double h0, const Ctl& c,
                   const double* lnA, std::vector<double>* hist = nullptr) {
@@ -421,7 +500,7 @@ Outcome integrate(const Sys& sys, double* y, double dt, double h0, const Ctl& c,
     if (h < c.h_min) { o.status = 2; break; }
     ++attempts;
     double hs = std::min(h, rem);
-    int rc = ros4_step(sys, y, lnA, hs, ynew.data(), err.data());
+    int rc = ros_step(sys, *c.mt, y, lnA, hs, c.estimator, ynew.data(), err.data());
     bool ok = rc == 0;
     double e = 0;
     if (ok) {
@@ -439,7 +518,7 @@ Outcome integrate(const Sys& sys, double* y, double dt, double h0, const Ctl& c,
       continue;
     }
     bad = 0;
-    double fac = (e > 0) ? c.safety * std::pow(e, -0.25) : c.fac_max;
+    double fac = (e > 0) ? c.safety * std::pow(e, -1.0 / c.mt->elo) : c.fac_max;
     if (e <= 1.0) {
       for (int i = 0; i < n; ++i) y[i] = ynew[i];
       rem -= hs;
@@ -486,7 +565,7 @@ void from_phi(const Mech& m, double P, const S* phi, S* T, S* Y) {
 
 // Replays one cell's accepted steps in dual arithmetic: the derivative of the
 // final (T, Y) along a direction in (ln A, T0, Y0).
-void tangent(const Mech& m, double P, double T0, const double* Y0, const double* lnA,
+void tangent(const Mech& m, const Method& mt, double P, double T0, const double* Y0, const double* lnA,
              const std::vector<double>& hs, const double* v_lnA, double dT0, const double* dY0,
              double* dT, double* dY) {
   typedef Dual<double> D;
@@ -497,7 +576,7 @@ void tangent(const Mech& m, double P, double T0, const double* Y0, const double*
   for (int k = 0; k < K; ++k) Y[k] = D{Y0[k], dY0 ? dY0[k] : 0.0};
   to_phi(m, D{T0, dT0}, P, Y.data(), phi.data());
   for (double h : hs) {
-    ros4_step(sys, phi.data(), la.data(), h, ynew.data(), err.data());
+    ros_step(sys, mt, phi.data(), la.data(), h, EST_EMBEDDED, ynew.data(), err.data());
     phi = ynew;
   }
   D T;
@@ -509,6 +588,8 @@ void tangent(const Mech& m, double P, double T0, const double* Y0, const double*
 }  // namespace
 
 // ============================================================== C interface
+// `method`: 0 ROS4, 1 ROS3, 2 RODAS3, 3 RODAS4; `estimator`: 0 embedded,
+// 1 filtered.  Functions taking them return -100 for an unknown method.
 extern "C" {
 
 void* or_mech_load(const char* path) {
@@ -555,14 +636,24 @@ int or_lu_solve(int n, const double* A, const double* b, double* x) {
   return 0;
 }
 
-void or_ros4_table(double* t) {
-  const double v[] = {GAM, A21, A31, A32, C21, C31, C32, C41, C42, C43, M1, M2, M3, M4, E1, E2, E3, E4};
-  for (int i = 0; i < 18; ++i) t[i] = v[i];
+// The transformed table of a method: t[0] = s, t[1] = gamma, t[2] = elo, then
+// a[6][6], c[6][6], m[6], e[6] (t has 3 + 84 entries).
+int or_method_table(int method, double* t) {
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
+  t[0] = mt->s; t[1] = mt->gamma; t[2] = mt->elo;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) { t[3 + 6 * i + j] = mt->a[i][j]; t[39 + 6 * i + j] = mt->c[i][j]; }
+  for (int j = 0; j < 6; ++j) { t[75 + j] = mt->m[j]; t[81 + j] = mt->e[j]; }
+  return 0;
 }
 
-int or_step(void* h, double P, const double* phi, double hs, double* phinew, double* err) {
+int or_step(void* h, double P, const double* phi, double hs, double* phinew, double* err, int method,
+            int estimator) {
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
   ChemSys sys{(const Mech*)h, P};
-  return ros4_step(sys, phi, (const double*)nullptr, hs, phinew, err) ? -1 : 0;
+  return ros_step(sys, *mt, phi, (const double*)nullptr, hs, estimator, phinew, err) ? -1 : 0;
 }
 
 void or_to_phi(void* h, double T, double P, const double* Y, double* phi) {
@@ -578,11 +669,15 @@ void or_from_phi(void* h, double P, const double* phi, double* T, double* Y) {
 int or_integrate(void* hm, int64_t n, const double* T, const double* P, const double* Y, int64_t ldY,
                  double dt, double rtol, double atol, double* h_io, double* T_out, double* Y_out,
                  int32_t* n_acc, int32_t* n_rej, int32_t* status, const double* lnA, int max_steps,
-                 int nthreads) {
+                 int nthreads, int method, int estimator) {
   const Mech& m = *(const Mech*)hm;
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
   if (nthreads <= 0) nthreads = omp_get_max_threads();
   Ctl c;
   c.rtol = rtol; c.atol = atol;
+  c.mt = mt;
+  c.estimator = estimator;
   if (max_steps > 0) c.max_steps = max_steps;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
   for (int64_t cell = 0; cell < n; ++cell) {
@@ -608,14 +703,18 @@ int or_integrate(void* hm, int64_t n, const double* T, const double* P, const do
 // One cell: integrate and return the accepted step sizes (capacity cap).
 int or_record_steps(void* hm, double T, double P, const double* Y, double dt, double rtol,
                     double atol, double h0, const double* lnA, double* hs, int cap, double* T_out,
-                    double* Y_out) {
+                    double* Y_out, int method, int estimator) {
   const Mech& m = *(const Mech*)hm;
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
   const int K = m.K, N = K + 1;
   std::vector<double> phi(N);
   to_phi(m, T, P, Y, phi.data());
   ChemSys sys{&m, P};
   Ctl c;
   c.rtol = rtol; c.atol = atol;
+  c.mt = mt;
+  c.estimator = estimator;
   std::vector<double> hist;
   Outcome o = integrate(sys, phi.data(), dt, h0, c, lnA, &hist);
   from_phi(m, P, phi.data(), T_out, Y_out);
@@ -627,14 +726,16 @@ int or_record_steps(void* hm, double T, double P, const double* Y, double dt, do
 
 // One cell: replay a given sequence of step sizes (frozen steps, no control).
 int or_replay(void* hm, double T, double P, const double* Y, const double* lnA, const double* hs,
-              int nh, double* T_out, double* Y_out) {
+              int nh, double* T_out, double* Y_out, int method) {
   const Mech& m = *(const Mech*)hm;
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
   const int N = m.K + 1;
   std::vector<double> phi(N), ynew(N), err(N);
   to_phi(m, T, P, Y, phi.data());
   ChemSys sys{&m, P};
   for (int i = 0; i < nh; ++i) {
-    if (ros4_step(sys, phi.data(), lnA, hs[i], ynew.data(), err.data())) return -1;
+    if (ros_step(sys, *mt, phi.data(), lnA, hs[i], EST_EMBEDDED, ynew.data(), err.data())) return -1;
     phi = ynew;
   }
   from_phi(m, P, phi.data(), T_out, Y_out);
@@ -643,45 +744,67 @@ int or_replay(void* hm, double T, double P, const double* Y, const double* lnA, 
 
 // One cell: directional derivative of the final (T, Y) along (v_lnA, dT0, dY0)
 // through the frozen steps hs.
-void or_tangent(void* hm, double T, double P, const double* Y, const double* lnA, const double* hs,
-                int nh, const double* v_lnA, double dT0, const double* dY0, double* dT, double* dY) {
+int or_tangent(void* hm, double T, double P, const double* Y, const double* lnA, const double* hs,
+               int nh, const double* v_lnA, double dT0, const double* dY0, double* dT, double* dY,
+               int method) {
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
   std::vector<double> h(hs, hs + nh);
-  tangent(*(const Mech*)hm, P, T, Y, lnA, h, v_lnA, dT0, dY0, dT, dY);
+  tangent(*(const Mech*)hm, *mt, P, T, Y, lnA, h, v_lnA, dT0, dY0, dT, dY);
+  return 0;
 }
 
 // Model problems for the integrator alone.  h_fixed > 0: fixed steps of that
 // size (no control).  Returns accepted steps (negative status on failure).
 int or_integrate_linear(int n, const double* A, double* y, double dt, double rtol, double atol,
-                        double h_fixed) {
+                        double h_fixed, int method, int estimator) {
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
   LinSys sys{n, A};
   if (h_fixed > 0) {
     std::vector<double> ynew(n), err(n);
     int steps = (int)std::llround(dt / h_fixed);
     for (int s = 0; s < steps; ++s) {
-      ros4_step(sys, y, (const double*)nullptr, h_fixed, ynew.data(), err.data());
+      ros_step(sys, *mt, y, (const double*)nullptr, h_fixed, estimator, ynew.data(), err.data());
       for (int i = 0; i < n; ++i) y[i] = ynew[i];
     }
     return steps;
   }
   Ctl c;
   c.rtol = rtol; c.atol = atol;
+  c.mt = mt;
+  c.estimator = estimator;
   Outcome o = integrate(sys, y, dt, 0.0, c, nullptr);
   return o.status ? -o.status : o.accepted;
 }
 
-int or_integrate_riccati(double* y, double dt, double rtol, double atol, double h_fixed) {
-  RiccatiSys sys;
+// One step of y' = A y: the new state and the error estimate.
+int or_linear_step(int n, const double* A, const double* y, double h, double* ynew, double* err,
+                   int method, int estimator) {
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
+  LinSys sys{n, A};
+  return ros_step(sys, *mt, y, (const double*)nullptr, h, estimator, ynew, err) ? -1 : 0;
+}
+
+int or_integrate_cubic(double* y, double dt, double rtol, double atol, double h_fixed, int method,
+                       int estimator) {
+  const Method* mt = method_of(method);
+  if (!mt) return -100;
+  CubicSys sys;
   if (h_fixed > 0) {
     double ynew, err;
     int steps = (int)std::llround(dt / h_fixed);
     for (int s = 0; s < steps; ++s) {
-      ros4_step(sys, y, (const double*)nullptr, h_fixed, &ynew, &err);
+      ros_step(sys, *mt, y, (const double*)nullptr, h_fixed, estimator, &ynew, &err);
       y[0] = ynew;
     }
     return steps;
   }
   Ctl c;
   c.rtol = rtol; c.atol = atol;
+  c.mt = mt;
+  c.estimator = estimator;
   Outcome o = integrate(sys, y, dt, 0.0, c, nullptr);
   return o.status ? -o.status : o.accepted;
 }

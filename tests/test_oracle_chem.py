@@ -135,6 +135,58 @@ def test_falloff_limits(ch4):
     assert seen["low"] > 10 and seen["high"] > 10
 
 
+def troe_mechanism(path, lnA, lnA0, a, T3, T1, T2):
+    """A (+M) = B + C as a Troe falloff reaction with b = theta = 0 for both
+    limits (so k_inf = A, k0 = A0) and no listed efficiencies ([M] = sum C)."""
+    nasa = "3.5 0 0 0 0 -1000.0 4.0"
+    text = ["CHEMMECH 1", "ELEMENTS 2 H O", "SPECIES 4",
+            "A 34.0 2 2 1000.0 %s %s" % (nasa, nasa),
+            "B 17.0 1 1 1000.0 %s %s" % (nasa, nasa),
+            "C 17.0 1 1 1000.0 %s %s" % (nasa, nasa),
+            "N2 28.0 0 0 1000.0 %s %s" % (nasa, nasa),
+            "REACTIONS 1",
+            "F 1 0 1 2 1 1 2 1 %r 0.0 0.0 0 %r 0.0 0.0 %r %r %r %r" % tuple(
+                float(v) for v in (lnA, lnA0, a, T3, T1, T2))]
+    with open(path, "w") as f:
+        f.write("\n".join(text) + "\n")
+    return path
+
+
+def troe_checks(o, T=1200.0, lnA=np.log(1e10), lnA0=np.log(1e12), T1=800.0):
+    """The Gilbert-Luther-Troe broadening factor at the points its form fixes.
+    With T3 = T1 and no T2 term, F_cent = exp(-T/T1) for any a.  With x =
+    log10 Pr + c and y = x / (n - d x), log10 F = log10 F_cent / (1 + y^2):
+    F = F_cent where x = 0, F = F_cent^(1/2) where y = +1 or -1, and F ->
+    F_cent^(1/(1 + 1/d^2)) as Pr -> 0 or infinity (c = -0.4 - 0.67 log10 F_cent,
+    n = 0.75 - 1.27 log10 F_cent, d = 0.14)."""
+    Fc = np.exp(-T / T1)
+    lFc = np.log10(Fc)
+    c = -0.4 - 0.67 * lFc
+    n = 0.75 - 1.27 * lFc
+    d = 0.14
+
+    def F_at(log10Pr):
+        M = 10.0 ** log10Pr * np.exp(lnA) / np.exp(lnA0)
+        Cc = np.array([0.25, 0.25, 0.25, 0.25]) * M
+        _, _, kf, _ = o.kinetics(T, 101325.0, Cc)
+        Pr = np.exp(lnA0) * M / np.exp(lnA)
+        return kf[0] / (np.exp(lnA) * Pr / (1.0 + Pr))
+
+    assert F_at(-c) == pytest.approx(Fc, rel=1e-12)
+    assert F_at(n / (1 + d) - c) == pytest.approx(np.sqrt(Fc), rel=1e-12)
+    assert F_at(-n / (1 - d) - c) == pytest.approx(np.sqrt(Fc), rel=1e-12)
+    lim = lFc / (1 + 1 / d ** 2)
+    for lp in (250.0, -250.0):
+        # x = +-250: y is within n / (d |x|) ~ 3 % of its limit -1/d
+        assert np.log10(F_at(lp)) == pytest.approx(lim, rel=0.1)
+
+
+def test_troe_broadening_special_points(tmp_path):
+    for a, T1 in ((0.3, 800.0), (0.8, 3000.0)):
+        path = troe_mechanism(str(tmp_path / "troe.txt"), np.log(1e10), np.log(1e12), a, T1, T1, 0.0)
+        troe_checks(oracle.Oracle(path), T1=T1)
+
+
 # ------------------------------------------------------------------ Jacobian
 @pytest.mark.parametrize("mech", ["small", "ch4"])
 def test_jacobian_vs_central_differences(mech, request):
@@ -248,6 +300,32 @@ def test_relaxation_to_gibbs_equilibrium(small):
         rev = kr[j] * np.prod([Cc[i] ** n for i, n in rx.prod])
         if fwd > 1e-20 * max(1.0, np.abs(q).max()) and fwd > 1e-30:
             assert abs(np.log(rev / fwd)) < 1e-4, (j, fwd, rev)
+    gibbs_equilibrium_checks(o, m, T, P, Y)
+
+
+def gibbs_equilibrium_checks(o, m, T, P, Y):
+    """At the relaxed state, each reaction's quotient of partial pressures in
+    atmospheres equals the thermodynamic K_p = exp(sum_k nu_k (s_k/R - h_k/RT))
+    (ideal gas, P_atm standard state).  A wrong standard-state factor in the
+    oracle's K_c (for example kmol against mol: 1000^sum nu) moves the
+    equilibrium the kinetics relax to, which this sees for reactions whose
+    sum nu is not zero."""
+    x = (Y / o.W) / (Y / o.W).sum()
+    cp, hRT, sR = o.thermo(T)
+    g = sR - hRT
+    checked = 0
+    for rx in m.reactions:
+        nu = np.zeros(o.K)
+        for i, n in rx.reac:
+            nu[i] -= n
+        for i, n in rx.prod:
+            nu[i] += n
+        if nu.sum() == 0 or np.any(x[nu != 0] < 1e-25):
+            continue
+        lnQ = nu @ np.log(x * P / 101325.0)
+        assert lnQ == pytest.approx(nu @ g, abs=1e-4), rx
+        checked += 1
+    assert checked >= 5
 
 
 def test_tight_tolerance_self_convergence(ch4):
@@ -286,7 +364,9 @@ def test_tangent_matches_central_differences(ch4):
         hs, Tf, Yf = o.record_steps(T[c], P[c], Y[:, c], 1e-5)
         v = rng.normal(size=o.Nr)
         dT, dY = o.tangent(T[c], P[c], Y[:, c], hs, v_lnA=v)
-        h = 1e-6
+        # h = 1e-5: over hundreds of stiff steps the replay's rounding, divided
+        # by 2h, is already ~1e-7 of the largest component at h = 1e-6
+        h = 1e-5
         Tp, Yp = o.replay(T[c], P[c], Y[:, c], hs, lnA=o.lnA + h * v)
         Tm, Ym = o.replay(T[c], P[c], Y[:, c], hs, lnA=o.lnA - h * v)
         fdT = (Tp - Tm) / (2 * h)
