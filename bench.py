@@ -1,19 +1,34 @@
 """Benchmark: cells integrated per second over one operator-splitting step.
 
-Workload (default): the CH4-shaped synthetic mechanism (53 species, 325
-reversible reactions, 30 third-body, 25 Troe) over 65,536 mixing-layer cells
-(P ~ U[1, 5] atm, Z ~ Beta(2, 5), T = linear mix of 300 K fuel and 800 K air
-plus N(0, 200^2) K), dt = 1e-6 s, FP64, rtol 1e-6, atol 1e-10.  One step = one
-chem_integrate call over every cell with the inputs resident in HBM.
+Headline workload (the metric's configuration that fits one GPU at its
+largest): the batching mix of the CH4-shaped synthetic mechanism (53 species,
+325 reversible reactions, 30 third-body, 25 Troe), 1,048,576 cells - 85 %
+cold (T < 800 K), 10 % stoichiometric at 1100-1400 K, 5 % burnt gas -
+dt = 1e-5 s, FP64, rtol 1e-6, atol 1e-10.  The library's autotuner runs once
+on the batch; one step is then one chem_integrate call (default launch) over
+every cell with the inputs resident in HBM.
 
-Prints one JSON line (rank 0).  Extra keys: "roofline" for the integrator
-kernel (algorithmic FP64 flops per launch over its average launch duration,
-measured with HIP events on the launch stream), "cpu_baseline" (the CPU
-oracle on a bounded sample of the same cells, on this host's cores), "modes"
-(cells/s of each launch mode of the library on this workload), "batching"
-(plain vs persistent launches on the batching mix, whose step counts differ
-by ~1000x between cells) and "adjoint" (discrete-adjoint vs forward time on
-the differentiation case).
+Prints one JSON line.  Besides the contract's keys:
+  "roofline"      the dominant kernel of the headline call: algorithmic FP64
+                  flops per launch (op-count model x the call's own step
+                  counts) over its average launch time, from HIP events on the
+                  launch stream;
+  "cpu_baseline"  the CPU oracle on a stratified 4,096-cell sample of the
+                  headline batch on this host's cores, with per-configuration
+                  samples and a single-core rate under "per_config";
+  "plain_vs_persistent"  the headline batch in the plain one-cell-per-thread
+                  launch and in the one-wavefront-per-cell launches (plain grid,
+                  persistent queue), all at full size;
+  "mixing"        the 65,536-cell mixing-layer case (dt = 1e-6 s) and each
+                  launch mode on it;
+  "large"         the 111-species mechanism (N = 112) on its mixing states;
+  "small"         the 10-species mechanism on 256 cells: per-call time of the
+                  plain, persistent and team launches and of a replayed
+                  captured graph (launch-overhead regime);
+  "methods"       the other solvers and the filtered error estimate on the
+                  mixing case;
+  "adjoint"       discrete-adjoint vs forward time on the 16,384-cell
+                  differentiation case.
 """
 from __future__ import annotations
 
@@ -30,9 +45,10 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 KERNEL_SOURCES = ["paper_2205_05681_amd/csrc/integrate.hip", "paper_2205_05681_amd/csrc/team.h",
-                  "paper_2205_05681_amd/csrc/kinetics.h", "paper_2205_05681_amd/csrc/ros4.h",
+                  "paper_2205_05681_amd/csrc/kinetics.h", "paper_2205_05681_amd/csrc/methods.h",
                   "paper_2205_05681_amd/csrc/mech.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_team_kernel_ch4_65536.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_team_kernel_batching_1048576.json")
+METRIC = "cells/s per split step at rtol 1e-6 (plain vs persistent); adjoint/forward cost"
 
 
 def kernel_hash():
@@ -43,96 +59,235 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def workload(name, synth, mech_dir):
-    if name == "ch4_mixing":
-        path, m = synth.mechanism_file("ch4", mech_dir)
-        T, P, Y = synth.states_mixing(m, 65536, 202)
-        desc = ("CH4-shaped synthetic mechanism (53 species, 325 reactions: 30 third-body, 25 Troe), "
-                "65,536 mixing-layer cells, P~U[1,5] atm, Z~Beta(2,5), dt=1e-6 s, rtol 1e-6, atol 1e-10")
-        return path, m, T, P, Y, 1e-6, desc
-    if name == "ch4_batching":
-        path, m = synth.mechanism_file("ch4", mech_dir)
-        T, P, Y, _ = synth.states_batching(m, 1048576, 203)
-        desc = ("CH4-shaped synthetic mechanism, 1,048,576 cells: 85% cold (<800 K), 10% stoichiometric "
-                "1100-1400 K, 5% burnt gas; dt=1e-5 s, rtol 1e-6, atol 1e-10")
-        return path, m, T, P, Y, 1e-5, desc
-    if name == "small":
-        path, m = synth.mechanism_file("small", mech_dir)
-        T, P, Y = synth.states_small(m, 256, 201)
-        desc = "H2/O2-shaped synthetic mechanism (10 species, 25 reactions), 256 cells, dt=1e-6 s"
-        return path, m, T, P, Y, 1e-6, desc
-    raise SystemExit("unknown workload %s" % name)
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
-def timed(fn, torch):
-    torch.cuda.synchronize()
+class Ctx:
+    def __init__(self, torch, np, chem, synth, opcount, dev, mech_dir):
+        self.torch, self.np, self.chem, self.synth, self.opcount = torch, np, chem, synth, opcount
+        self.dev, self.mech_dir = dev, mech_dir
+
+    def d(self, x):
+        return self.torch.from_numpy(self.np.ascontiguousarray(x)).to(self.dev)
+
+    def sync(self):
+        self.torch.cuda.synchronize()
+
+
+def timed(c, fn, reps=1):
+    c.sync()
     t = time.perf_counter()
-    fn()
-    torch.cuda.synchronize()
-    return time.perf_counter() - t
+    for _ in range(reps):
+        fn()
+    c.sync()
+    return (time.perf_counter() - t) / reps
 
 
-def batching(chem, synth, torch, np, mech_dir, n, dev):
-    """The batching mix (85 % cold, 10 % near ignition at stoichiometric
-    mixture fraction, 5 % burnt gas; dt = 1e-5 s) on n cells: cells/s of the
-    plain and persistent one-cell-per-thread launches (cells in index order
-    and hottest first) and of the one-wavefront-per-cell launches, one timed
-    call each after a warm-up call on 256 cells."""
-    path, m = synth.mechanism_file("ch4", mech_dir)
-    T, P, Y, kind = synth.states_batching(m, n, 203)
+def run_stats(c, mech, m, Tt, Pt, Yt, dt, **kw):
+    """One call with step counters: (attempts, accepted, rejected, n_steps, status)."""
+    stats = c.torch.zeros(3, dtype=c.torch.int64, device=c.dev)
+    r = c.chem.integrate(mech, Tt, Pt, Yt, dt, opts=c.chem.default_opts(stats=stats, **kw))
+    c.sync()
+    a, acc, rej = (int(x) for x in stats.cpu().numpy())
+    return a, acc, rej, r[3].cpu().numpy(), r[4].cpu().numpy()
+
+
+def headline(c, a):
+    """The batching mix at full size: autotune, then W warm-up and K timed
+    calls of the default launch."""
+    np, chem, synth = c.np, c.chem, c.synth
+    path, m = synth.mechanism_file("ch4", c.mech_dir)
+    T, P, Y, kind = synth.states_batching(m, a.cells, 203)
+    n = T.size
     mech = chem.Mechanism(path, device=0)
-    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-    Tt, Pt, Yt = d(T), d(P), d(Y)
-    out = {"workload": "CH4-shaped mechanism, %d cells drawn with the 1,048,576-cell batching recipe "
-                       "(85%% cold <800 K, 10%% stoichiometric 1100-1400 K, 5%% burnt gas), dt=1e-5 s" % n,
-           "cells": n, "cells_per_s": {}}
-    ns = None
-    runs = (("plain", 0), ("persistent", 0), ("plain", 1), ("persistent", 1), ("team", 1),
-            ("team_persistent", 1))
-    for mode, order in runs:
-        o = chem.default_opts(mode=mode, order=order)
-        chem.integrate(mech, Tt[:256], Pt[:256], Yt[:, :256].contiguous(), 1e-5, opts=o)
-        res = {}
+    Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
+    T1, Y1 = c.torch.empty_like(Tt), c.torch.empty_like(Yt)
+    h = c.torch.zeros(n, dtype=c.torch.float64, device=c.dev)
+    ns = c.torch.empty(n, dtype=c.torch.int32, device=c.dev)
+    st = c.torch.empty(n, dtype=c.torch.int32, device=c.dev)
+    log("headline: autotune")
+    chosen, cand_ms = chem.autotune(mech, Tt, Pt, Yt, 1e-5)
+    opts = chem.default_opts()
+    for _ in range(a.warmup):
+        h.zero_()
+        chem.integrate(mech, Tt, Pt, Yt, 1e-5, h=h, opts=opts, out=(T1, Y1), n_steps=ns, status=st)
+    c.sync()
+    log("headline: timed steps")
+    stream = c.torch.cuda.current_stream()
+    ev = [(c.torch.cuda.Event(enable_timing=True), c.torch.cuda.Event(enable_timing=True))
+          for _ in range(a.steps)]
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        h.zero_()
+        ev[i][0].record(stream)
+        chem.integrate(mech, Tt, Pt, Yt, 1e-5, h=h, opts=opts, out=(T1, Y1), n_steps=ns, status=st)
+        ev[i][1].record(stream)
+    c.sync()
+    wall = time.perf_counter() - t0
+    launch_ms = [s.elapsed_time(e) for s, e in ev]
+    status = st.cpu().numpy()
+    steps = ns.cpu().numpy()
+    att, acc, rej, _, _ = run_stats(c, mech, m, Tt, Pt, Yt, 1e-5)
+    flops, trans = c.opcount.batch_flops(m, att, acc)
+    avg_s = float(np.mean(launch_ms)) / 1e3
+    achieved = flops / avg_s / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("kernel_hash") == kernel_hash() and tf.get("cells") == n:
+            traffic = tf.get("hbm_bytes_per_launch")
+    modes = {1: "plain", 2: "persistent", 3: "team", 4: "team_persistent"}
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 6), "traffic": traffic,
+                "kernel": "integrate_team_kernel<56>" if chosen.mode in (3, 4) else "integrate_thread_kernel",
+                "flops_per_launch": flops, "transcendentals_per_launch": trans,
+                "attempted_steps": att, "accepted_steps": acc, "rejected_steps": rej,
+                "avg_launch_ms": round(avg_s * 1e3, 4)}
+    out = dict(value=n / (wall / a.steps), ms_per_step=wall * 1e3 / a.steps, roofline=roofline,
+               config={"workload": "batching mix: CH4-shaped synthetic mechanism (53 species, 325 reactions: "
+                                   "30 third-body, 25 Troe), 1,048,576 cells (85% cold <800 K, 10% stoichiometric "
+                                   "1100-1400 K, 5% burnt gas), dt=1e-5 s, rtol 1e-6, atol 1e-10, ROS4, "
+                                   "autotuned launch" if n == 1048576 else "batching mix, %d cells" % n,
+                       "cells": n, "species": m.n_species, "reactions": len(m.reactions), "dt": 1e-5,
+                       "rtol": 1e-6, "atol": 1e-10, "method": "ros4",
+                       "autotuned": {"mode": modes.get(chosen.mode, chosen.mode),
+                                     "waves_per_cu": chosen.waves_per_cu, "candidates_ms": cand_ms},
+                       "failed_cells": int((status != 0).sum()),
+                       "accepted_steps": {k: {"mean": round(float(steps[kind == i].mean()), 2),
+                                              "max": int(steps[kind == i].max())}
+                                          for i, k in enumerate(("cold", "igniting", "burnt"))},
+                       "step_spread": int(steps.max()) / max(1, int(steps.min()))})
+    # plain vs persistent at full size
+    pvp = {}
+    if not a.quick:
+        for label, mode in (("team_plain_grid", "team"), ("team_persistent", "team_persistent"),
+                            ("thread_plain", "plain")):
+            log("headline: %s" % label)
+            o = chem.default_opts(mode=mode)
+            t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-5, opts=o, out=(T1, Y1)))
+            pvp[label] = round(n / t, 1)
+        pvp["autotuned_default"] = round(out["value"], 1)
+        pvp["persistent_over_plain_team"] = round(pvp["team_persistent"] / pvp["team_plain_grid"], 3)
+        pvp["default_over_thread_plain"] = round(out["value"] / pvp["thread_plain"], 2)
+    out["plain_vs_persistent"] = pvp
+    mech.close()
+    return out, (path, m, T, P, Y, kind)
 
-        def run():
-            res["r"] = chem.integrate(mech, Tt, Pt, Yt, 1e-5, opts=o)
-        el = timed(run, torch)
-        out["cells_per_s"][mode + ("" if order else "_index_order")] = round(n / el, 1)
-        ns = res["r"][3].cpu().numpy()
-        assert int((res["r"][4] != 0).sum()) == 0, "failed cells in the batching mix"
-    out["accepted_steps"] = {k: {"mean": round(float(ns[kind == i].mean()), 2), "max": int(ns[kind == i].max())}
-                             for i, k in enumerate(("cold", "igniting", "burnt"))}
-    cps = out["cells_per_s"]
-    # one cell per thread in index order is the plain baseline of the comparison
-    base = cps["plain_index_order"]
-    out["over_plain_index_order"] = {k: round(v / base, 3) for k, v in cps.items()}
+
+def mixing(c, a):
+    """The 65,536-cell mixing-layer case, each launch mode."""
+    chem, synth = c.chem, c.synth
+    path, m = synth.mechanism_file("ch4", c.mech_dir)
+    T, P, Y = synth.states_mixing(m, 65536, 202)
+    n = T.size
+    mech = chem.Mechanism(path, device=0)
+    Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
+    out = {"workload": "CH4-shaped mechanism, 65,536 mixing-layer cells, P~U[1,5] atm, Z~Beta(2,5), dt=1e-6 s",
+           "cells_per_s": {}}
+    for mode in ("auto", "team", "team_persistent", "plain", "persistent"):
+        o = chem.default_opts(mode=mode)
+        chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o)
+        reps = 1 if mode in ("plain", "persistent") else 3
+        t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o), reps)
+        out["cells_per_s"][mode] = round(n / t, 1)
+        if mode == "auto":
+            out["ms_per_call"] = round(t * 1e3, 3)
+    att, acc, rej, ns, _ = run_stats(c, mech, m, Tt, Pt, Yt, 1e-6)
+    out.update(attempted_steps=att, accepted_steps=acc, rejected_steps=rej,
+               accepted_steps_max=int(ns.max()))
     mech.close()
     return out
 
 
-def adjoint_cost(chem, synth, torch, np, mech_dir, n, dev):
-    """Differentiation case: n mixing-layer cells, dt = 1e-5 s, losses final T
-    and sum_k w_k Y_k; times of the plain forward call, the checkpointed
-    forward call (two passes) and the discrete adjoint (gradients with
-    respect to every ln A summed over cells, and the initial state)."""
-    path, m = synth.mechanism_file("ch4", mech_dir)
+def methods(c, a):
+    """Cells/s of each solver and of the filtered estimate on the mixing case
+    (default launch), with their step counts."""
+    chem, synth = c.chem, c.synth
+    path, m = synth.mechanism_file("ch4", c.mech_dir)
+    T, P, Y = synth.states_mixing(m, 65536, 202)
+    n = T.size
+    mech = chem.Mechanism(path, device=0)
+    Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
+    out = {}
+    for meth in ("ros4", "ros3", "rodas3", "rodas4"):
+        for est in ("embedded", "filtered"):
+            o = chem.default_opts(method=meth, estimator=est)
+            chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o)
+            t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o), 2)
+            att, acc, rej, _, _ = run_stats(c, mech, m, Tt, Pt, Yt, 1e-6, method=meth, estimator=est)
+            out["%s_%s" % (meth, est)] = {"cells_per_s": round(n / t, 1), "accepted": acc, "rejected": rej}
+    mech.close()
+    return out
+
+
+def large(c, a):
+    """The 111-species mechanism (N = 112) on its mixing-layer states."""
+    chem, synth = c.chem, c.synth
+    path, m = synth.mechanism_file("large", c.mech_dir)
+    T, P, Y = synth.states_mixing(m, 262144, 204)
+    n = min(a.large_cells, T.size)
+    T, P, Y = T[:n], P[:n], Y[:, :n]
+    mech = chem.Mechanism(path, device=0)
+    Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
+    chem.integrate(mech, Tt[:64], Pt[:64], Yt[:, :64].contiguous(), 1e-5)
+    t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-5))
+    att, acc, rej, ns, st = run_stats(c, mech, m, Tt, Pt, Yt, 1e-5)
+    flops, _ = c.opcount.batch_flops(m, att, acc)
+    mech.close()
+    return {"workload": "111-species mechanism (784 reactions: 60 third-body, 40 Troe), the first %d of the "
+                        "262,144 mixing-layer cells, dt=1e-5 s" % n,
+            "cells": n, "cells_per_s": round(n / t, 1), "ms_per_call": round(t * 1e3, 3),
+            "attempted_steps": att, "accepted_steps": acc, "failed_cells": int((st != 0).sum()),
+            "fp64_tflops": round(flops / t / 1e12, 4), "frac": round(flops / t / 1e12 / FP64_PEAK_TFLOPS, 6)}
+
+
+def small(c, a):
+    """10 species, 256 cells, dt = 1e-6 s: per-call times of the launches and of a
+    replayed captured graph (the default launch)."""
+    chem, synth = c.chem, c.synth
+    path, m = synth.mechanism_file("small", c.mech_dir)
+    T, P, Y = synth.states_small(m, 256, 201)
+    mech = chem.Mechanism(path, device=0)
+    Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
+    out = {"workload": "H2/O2-shaped mechanism (10 species, 25 reactions), 256 cells, dt=1e-6 s", "ms_per_call": {}}
+    for mode in ("plain", "persistent", "team", "team_persistent", "auto"):
+        o = chem.default_opts(mode=mode)
+        chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o)
+        out["ms_per_call"][mode] = round(timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o), 20) * 1e3, 4)
+    T1, Y1 = c.torch.empty_like(Tt), c.torch.empty_like(Yt)
+    g = chem.Graph(mech, Tt, Pt, Yt, 1e-6, out=(T1, Y1))
+    g.launch()
+    out["ms_per_call"]["graph_auto"] = round(timed(c, g.launch, 20) * 1e3, 4)
+    g.close()
+    mech.close()
+    return out
+
+
+def adjoint_cost(c, a):
+    """Differentiation case: 16,384 mixing-layer cells, dt = 1e-5 s, loss
+    T_final + sum_k w_k Y_k; times of the plain forward call, the checkpointed
+    forward call (two passes) and the discrete adjoint (gradients with respect
+    to every ln A summed over cells, and the initial state)."""
+    chem, synth, np = c.chem, c.synth, c.np
+    path, m = synth.mechanism_file("ch4", c.mech_dir)
+    n = a.adjoint_cells
     T, P, Y = synth.states_mixing(m, n, 205)
     w = synth.loss_weights(m)
     mech = chem.Mechanism(path, device=0)
-    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-    Tt, Pt, Yt = d(T), d(P), d(Y)
-    gT = torch.ones(n, dtype=torch.float64, device=dev)
-    gY = d(np.repeat(w[:, None], n, 1))
+    Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
+    gT = c.torch.ones(n, dtype=c.torch.float64, device=c.dev)
+    gY = c.d(np.repeat(w[:, None], n, 1))
     chem.integrate(mech, Tt[:256], Pt[:256], Yt[:, :256].contiguous(), 1e-5)
-    t_fwd = min(timed(lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-5), torch) for _ in range(2))
+    t_fwd = min(timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-5)) for _ in range(2))
     res = {}
 
     def fwd_ck():
         res["ck"] = chem.integrate(mech, Tt, Pt, Yt, 1e-5, checkpoint=True)[5]
-    t_ck = timed(fwd_ck, torch)
+    t_ck = timed(c, fwd_ck)
     ck = res["ck"]
     recs = int(ck.records())
-    t_adj = timed(lambda: chem.adjoint(mech, ck, gT, gY, per_cell=False, initial=True), torch)
+    t_adj = timed(c, lambda: chem.adjoint(mech, ck, gT, gY, per_cell=False, initial=True))
     ck.close()
     mech.close()
     return {"workload": "CH4-shaped mechanism, %d mixing-layer cells, dt=1e-5 s, d(T_final + sum w_k Y_k)"
@@ -143,46 +298,76 @@ def adjoint_cost(chem, synth, torch, np, mech_dir, n, dev):
             "gradient_over_forward": round((t_ck + t_adj) / t_fwd, 3)}
 
 
-def cpu_baseline(oracle, path, T, P, Y, dt, budget_s):
-    """The oracle (as it is) on the first cells of the workload, in chunks of
-    512, until about budget_s seconds of CPU work."""
+def oracle_rate(oracle, path, T, P, Y, dt, budget_s, threads=0, chunk=256):
+    """The oracle (as it is) on the given cells in order, in chunks, until about
+    budget_s seconds of wall time; returns (cells/s, cells done, seconds, threads)."""
     import numpy as np
     o = oracle.Oracle(path)
-    done, t0, threads = 0, time.time(), 0
+    done, t0, thr = 0, time.time(), 0
     n = T.size
     while done < n and (time.time() - t0) < budget_s:
-        c = slice(done, min(done + 512, n))
-        r = o.integrate(T[c], P[c], np.ascontiguousarray(Y[:, c]), dt)
-        threads = r["threads"]
-        done = c.stop
+        s = slice(done, min(done + chunk, n))
+        r = o.integrate(T[s], P[s], np.ascontiguousarray(Y[:, s]), dt, nthreads=threads)
+        thr = r["threads"]
+        done = s.stop
     el = time.time() - t0
-    return {"value": done / el, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
-            "sample": "first %d of the %d cells, %.1f s wall on %d threads" % (done, n, el, threads)}
+    return done / el, done, el, thr
+
+
+def cpu_baseline(c, a, head):
+    """The oracle on a stratified 4,096-cell sample of the headline batch (the
+    85/10/5 mix kept, cells shuffled), on all host threads; per configuration
+    the oracle on a bounded sample of that workload, and one core."""
+    import oracle
+    np, synth = c.np, c.synth
+    path, m, T, P, Y, kind = head
+    rng = np.random.default_rng(7)
+    idx = np.concatenate([rng.choice(np.flatnonzero(kind == k), int(round(f * 4096)), replace=False)
+                          for k, f in ((0, 0.85), (1, 0.10), (2, 0.05))])
+    idx = rng.permutation(idx)
+    v, done, el, thr = oracle_rate(oracle, path, T[idx], P[idx], Y[:, idx], 1e-5, 1e9)
+    out = {"value": round(v, 1), "unit": "cells/s", "cores": int(thr), "kind": "oracle",
+           "sample": "stratified 4,096 cells of the 1,048,576-cell batching mix (3,482 cold, 410 igniting, "
+                     "205 burnt; shuffled), %.1f s wall on %d threads" % (el, thr), "per_config": {}}
+    pc = out["per_config"]
+    v1, d1, e1, _ = oracle_rate(oracle, path, T[idx], P[idx], Y[:, idx], 1e-5, a.cpu_seconds / 2, threads=1,
+                                chunk=32)
+    pc["batching_single_core"] = {"cells_per_s": round(v1, 2), "cells": d1, "seconds": round(e1, 1)}
+    p2, m2 = synth.mechanism_file("ch4", c.mech_dir)
+    T2, P2, Y2 = synth.states_mixing(m2, 65536, 202)
+    v, d_, e_, t_ = oracle_rate(oracle, p2, T2, P2, Y2, 1e-6, a.cpu_seconds)
+    pc["mixing_65536"] = {"cells_per_s": round(v, 1), "cells": d_, "seconds": round(e_, 1), "threads": t_,
+                          "sample": "first cells of the batch"}
+    p1, m1 = synth.mechanism_file("small", c.mech_dir)
+    T1, P1, Y1 = synth.states_small(m1, 256, 201)
+    v, d_, e_, t_ = oracle_rate(oracle, p1, T1, P1, Y1, 1e-6, 1e9)
+    pc["small_256"] = {"cells_per_s": round(v, 1), "cells": d_, "seconds": round(e_, 1), "threads": t_}
+    p4, m4 = synth.mechanism_file("large", c.mech_dir)
+    T4, P4, Y4 = synth.states_mixing(m4, 262144, 204)
+    sel = np.random.default_rng(9).permutation(T4.size)[:8192]
+    v, d_, e_, t_ = oracle_rate(oracle, p4, T4[sel], P4[sel], Y4[:, sel], 1e-5, a.cpu_seconds, chunk=64)
+    pc["large_262144"] = {"cells_per_s": round(v, 1), "cells": d_, "seconds": round(e_, 1), "threads": t_,
+                          "sample": "random cells of the batch"}
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ch4_mixing")
-    ap.add_argument("--mode", default="auto", help="headline launch mode")
-    ap.add_argument("--compare", default="team,plain,persistent",
-                    help="other modes to time (thread-per-cell modes take one step)")
-    ap.add_argument("--order", default="hot", choices=["hot", "index"],
-                    help="dispatch order of the cells: hottest first (library default) or index order")
-    ap.add_argument("--batching-cells", type=int, default=65536,
-                    help="cells of the batching-mix comparison (0: skip)")
-    ap.add_argument("--adjoint-cells", type=int, default=16384,
-                    help="cells of the adjoint/forward cost measurement (0: skip)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cells", type=int, default=1048576, help="headline batch size")
+    ap.add_argument("--large-cells", type=int, default=4096)
+    ap.add_argument("--adjoint-cells", type=int, default=16384)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--skip", default="", help="comma list of legs to skip: mixing,methods,large,small,adjoint")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported "
-              "(cells are independent: several GPUs would each take a contiguous share of the batch)" % a.gpus, file=sys.stderr)
+              "(cells are independent: several GPUs would each take a contiguous share of the batch)" % a.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -191,141 +376,37 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    mech_dir = tempfile.mkdtemp(prefix="chem_bench_")
-    path, m, T, P, Y, dt, desc = workload(a.workload, synth, mech_dir)
-    n = T.size
-    mech = chem.Mechanism(path, device=0)
-    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
-    Tt, Pt, Yt = d(T), d(P), d(Y)
-    T1 = torch.empty_like(Tt)
-    Y1 = torch.empty_like(Yt)
-    h = torch.zeros(n, dtype=torch.float64, device=dev)
-    ns = torch.empty(n, dtype=torch.int32, device=dev)
-    st = torch.empty(n, dtype=torch.int32, device=dev)
-
-    order = {"hot": 1, "index": 0}[a.order]
-
-    def step(mode):
-        h.zero_()
-        chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=chem.default_opts(mode=mode, order=order),
-                       out=(T1, Y1), n_steps=ns, status=st)
-
-    if a.calibrate_copy:
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    # ---- headline mode: W warmup steps, then K timed steps
-    for _ in range(a.warmup):
-        step(a.mode)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
-    opts = chem.default_opts(mode=a.mode, order=order)
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        h.zero_()
-        ev[i][0].record(stream)
-        chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=opts, out=(T1, Y1), n_steps=ns, status=st)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = [s.elapsed_time(e) for s, e in ev]
-    ms_per_step = wall * 1e3 / a.steps
-    value = n / (wall / a.steps)
-    status = st.cpu().numpy()
-    steps_acc = ns.cpu().numpy()
-
-    # ---- step statistics of the same call (deterministic), for the op count
-    stats = torch.zeros(3, dtype=torch.int64, device=dev)
-    h.zero_()
-    chem.integrate(mech, Tt, Pt, Yt, dt, h=h, opts=chem.default_opts(mode=a.mode, order=order, stats=stats), out=(T1, Y1))
-    torch.cuda.synchronize()
-    attempts, accepted, rejected = (int(x) for x in stats.cpu().numpy())
-    flops, trans = opcount.batch_flops(m, attempts, accepted)
-    avg_launch_s = float(np.mean(launch_ms)) / 1e3
-    achieved = flops / avg_launch_s / 1e12
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tf = json.load(open(TRAFFIC_FILE))
-        if tf.get("kernel_hash") == kernel_hash() and tf.get("workload") == a.workload:
-            traffic = tf.get("hbm_bytes_per_launch")
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 6), "traffic": traffic,
-                "kernel": "integrate_team_kernel" if a.mode in ("auto", "team", "team_persistent") else
-                "integrate_thread_kernel",
-                "flops_per_launch": flops, "transcendentals_per_launch": trans,
-                "attempted_steps": attempts, "accepted_steps": accepted,
-                "avg_launch_ms": round(avg_launch_s * 1e3, 4)}
-
-    # ---- warm start: each cell's last internal step carried over as its next
-    # initial step (the coupling's reuse of h between split steps), same inputs
-    hw = torch.zeros(n, dtype=torch.float64, device=dev)
-    chem.integrate(mech, Tt, Pt, Yt, dt, h=hw, opts=opts, out=(T1, Y1))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        chem.integrate(mech, Tt, Pt, Yt, dt, h=hw, opts=opts, out=(T1, Y1))
-    torch.cuda.synchronize()
-    warm_wall = time.perf_counter() - t0
-    wstats = torch.zeros(3, dtype=torch.int64, device=dev)
-    chem.integrate(mech, Tt, Pt, Yt, dt, h=hw, opts=chem.default_opts(mode=a.mode, order=order, stats=wstats),
-                   out=(T1, Y1))
-    torch.cuda.synchronize()
-    w_att, w_acc, _ = (int(x) for x in wstats.cpu().numpy())
-    warm = {"value": round(n / (warm_wall / a.steps), 1), "unit": "cells/s",
-            "ms_per_step": round(warm_wall * 1e3 / a.steps, 4),
-            "attempted_steps": w_att, "accepted_steps": w_acc,
-            "note": "same inputs, h_io carried over from the previous call"}
-
-    # ---- other launch modes on the same cells
-    modes = {a.mode: round(value, 1)}
-    for mode in [x for x in a.compare.split(",") if x and x != a.mode]:
-        reps = 1 if mode in ("plain", "persistent") else max(1, a.steps // 2)
-        step(mode)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            step(mode)
-        torch.cuda.synchronize()
-        modes[mode] = round(n / ((time.perf_counter() - t) / reps), 1)
-
-    mech.close()
-    batch = batching(chem, synth, torch, np, mech_dir, a.batching_cells, dev) if a.batching_cells else None
-    adj = adjoint_cost(chem, synth, torch, np, mech_dir, a.adjoint_cells, dev) if a.adjoint_cells else None
-
-    cpu = None
-    if not a.no_cpu:
-        import oracle
-        cpu = cpu_baseline(oracle, path, T, P, Y, dt, a.cpu_seconds)
-
+    c = Ctx(torch, np, chem, synth, opcount, dev, tempfile.mkdtemp(prefix="chem_bench_"))
+    head, head_data = headline(c, a)
+    skip = set(a.skip.split(",")) if a.skip else set()
+    if a.quick:
+        skip |= {"mixing", "methods", "large", "small", "adjoint"}
+    legs = {}
+    for name, fn in (("mixing", mixing), ("methods", methods), ("large", large), ("small", small),
+                     ("adjoint", adjoint_cost)):
+        if name not in skip:
+            log("leg: %s" % name)
+            legs[name] = fn(c, a)
+    cpu = None if a.no_cpu else cpu_baseline(c, a, head_data)
     out = {
-        "metric": "cells/s per split step at rtol 1e-6 (plain vs persistent); adjoint/forward cost",
-        "value": round(value, 1),
+        "metric": METRIC,
+        "value": round(head["value"], 1),
         "unit": "cells/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(head["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "cells": n, "species": m.n_species, "reactions": len(m.reactions),
-                   "dt": dt, "rtol": 1e-6, "atol": 1e-10, "mode": a.mode, "order": a.order,
-                   "failed_cells": int((status != 0).sum()),
-                   "accepted_steps_mean": round(float(steps_acc.mean()), 3),
-                   "accepted_steps_max": int(steps_acc.max())},
-        "roofline": roofline,
+        "config": head["config"],
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
-        "modes": modes,
-        "warm_start": warm,
-        "batching": batch,
-        "adjoint": adj,
+        "plain_vs_persistent": head["plain_vs_persistent"],
     }
+    out.update(legs)
     print(json.dumps(out), flush=True)
 
 

@@ -1,14 +1,15 @@
 /*
- * chem.h - C ABI of the batched FP64 ROS4 chemistry integrator for MI355X (gfx950).
+ * chem.h - C ABI of the batched FP64 Rosenbrock (ROS4) chemistry integrator for MI355X (gfx950).
  *
  * Every cell of a CFD domain (or sub-domain) is advanced independently over one
  * operator-splitting step at constant pressure.  The state of a cell is
  * Phi = {T, V, n_1 .. n_{K-1}} per unit mass, the last species being the bath
  * gas closed by the ideal-gas law (paper Sec. 2.1, eqs. (state_vec), (n_nsp)).
- * Each cell is integrated with the four-stage, fourth-order linearly implicit
- * Rosenbrock method ROS4 in the transformed form of Sec. 2.3 (one LU of
- * (I/(h gamma) - J) per step, analytical Jacobian J of eq. (jac)), with
- * adaptive steps from rtol/atol (Sec. 3.1).  One batched call integrates all
+ * Each cell is integrated with a linearly implicit Rosenbrock method of the
+ * paper's solver table (Table T:solvers) - the four-stage, fourth-order ROS4
+ * by default, or ROS3, RODAS3, RODAS4 - in the transformed form of Sec. 2.3
+ * (one LU of (I/(h gamma) - J) per step, analytical Jacobian J of eq. (jac)),
+ * with adaptive steps from rtol/atol (Sec. 3.1).  One batched call integrates all
  * cells, and each cell's last internal step is returned for reuse as its next
  * initial step (Sec. 2.4.1, the batched chemistry model).
  *
@@ -44,7 +45,10 @@ extern "C" {
 #define CHEM_EPARSE (-2)       /* mechanism file missing or malformed */
 #define CHEM_EHIP (-3)         /* HIP runtime error */
 #define CHEM_ENOMEM (-4)       /* device allocation failed */
-#define CHEM_EUNSUPPORTED (-5) /* mechanism larger than the compiled limits */
+#define CHEM_EUNSUPPORTED (-5) /* mechanism larger than the compiled limits, or a method the
+                                  call does not support (the adjoint is ROS4 only) */
+#define CHEM_ENONDET (-6)      /* checkpointed integration: the recording pass took other
+                                  steps than the counting pass (a non-deterministic launch) */
 
 /* ---- per-cell outcome (status[cell]) ----------------------------------- */
 #define CHEM_CELL_OK 0
@@ -69,6 +73,21 @@ extern "C" {
                                    cells of similar cost also share a wavefront in the
                                    one-cell-per-thread modes.  Results do not depend on it. */
 
+/* ---- integration method (chem_opts.method), Table T:solvers ------------ */
+#define CHEM_METHOD_ROS4 0      /* 4 stages, order 4(3), Hairer-Wanner L-stable set (default) */
+#define CHEM_METHOD_ROS3 1      /* 3 stages, order 3(2), Sandu et al. */
+#define CHEM_METHOD_RODAS3 2    /* 4 stages, order 3(2), stiffly accurate, Sandu et al. */
+#define CHEM_METHOD_RODAS4 3    /* 6 stages, order 4(3), stiffly accurate, Hairer-Wanner */
+
+/* ---- error estimate (chem_opts.estimator) ------------------------------ */
+#define CHEM_EST_EMBEDDED 0     /* the method's own: difference of the two solutions */
+#define CHEM_EST_FILTERED 1     /* the same, times (I - h gamma J)^-1 (one more solve per
+                                   step): keeps the h^elo term, takes the estimate of a
+                                   strongly damped mode to zero.  For ROS4 the embedded
+                                   solution keeps 0.55 of such a mode, so the embedded
+                                   estimate rejects steps that relax fast transients;
+                                   the filtered one is less conservative at a given tol. */
+
 typedef struct chem_mech_s* chem_mech_t; /* opaque, library-owned */
 typedef struct chem_graph_s* chem_graph_t; /* opaque, library-owned captured split step */
 typedef struct chem_ckpt_s* chem_ckpt_t; /* opaque, library-owned adjoint checkpoint */
@@ -86,6 +105,11 @@ typedef struct {
   int32_t wg_size;        /* work-group size in threads (0 = library choice) */
   int32_t waves_per_cu;   /* persistent modes: resident waves per CU (0 = occupancy limit) */
   int32_t order;          /* dispatch order of the cells: CHEM_ORDER_* (CHEM_ORDER_HOT_FIRST) */
+  int32_t method;         /* CHEM_METHOD_* (CHEM_METHOD_ROS4) */
+  int32_t estimator;      /* CHEM_EST_* (CHEM_EST_EMBEDDED) */
+  int32_t team_waves;     /* team modes: wavefronts per cell; 0 = library choice (one per cell
+                             for N <= 64, which is the only size built: other values are
+                             CHEM_EINVAL) */
   unsigned long long* stats; /* nullable DEVICE pointer to 3 counters that the call adds to:
                                 attempted steps, accepted steps, rejected steps (all cells) */
 } chem_opts;
@@ -107,11 +131,18 @@ int chem_mech_info(chem_mech_t m, int32_t* n_species, int32_t* n_reactions, int3
  * (synchronises the device). */
 void chem_mech_free(chem_mech_t m);
 
-/* Integrate n_cells cells over [0, dt] (one split step).
+/* Integrate n_cells cells over [0, dt] (one split step): the batched
+ * chemistry integration of Sec. 2.4.1 - every cell advanced independently at
+ * constant pressure (Sec. 2.1), from (T, P, Y) converted to the state of
+ * eq. (state_vec) through eq. (conc_form1) and back, by the Rosenbrock method
+ * of Sec. 2.3 with the analytical Jacobian of eq. (jac) and adaptive steps
+ * from rtol/atol (Sec. 3.1).
  *   T_in[n], P[n], Y_in[K][ldY]  initial temperature, pressure, mass fractions
  *   T_out[n], Y_out[K][ldY]      results; may alias T_in / Y_in
+ *   dt        split-step length (> 0); rtol (> 0), atol (>= 0) the tolerances
  *   h_io[n]   nullable; in: first step per cell (<= 0 means dt), out: the
- *             controller's next step after the last accepted one
+ *             controller's next step after the last accepted one (the step
+ *             reused by the next split step, Sec. 2.4.1)
  *   n_steps[n], status[n]  nullable int32 outputs: accepted steps, outcome
  *   lnA[Nr]   nullable; replaces every reaction's ln A (falloff reactions
  *             move their low-pressure A by the same factor), for
@@ -121,9 +152,14 @@ void chem_mech_free(chem_mech_t m);
  *             the adjoint recomputes the stage vectors) for
  *             chem_integrate_adjoint; *ckpt_out receives a new checkpoint
  *             that the caller frees.  This runs the integration twice (a
- *             counting pass sizes the record arena) and synchronises the
- *             stream; the counting pass writes only library scratch
- * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM.  Asynchronous on `stream`. */
+ *             counting pass sizes the record arena, both passes with the same
+ *             resolved options) and synchronises the stream; the counting pass
+ *             writes only library scratch
+ * All pointers are device pointers owned by the caller.  The library uses a
+ * per-(handle, stream) workspace that it allocates on first use and grows.
+ * Errors: CHEM_EINVAL (null pointer, n < 0, dt <= 0, rtol <= 0, atol < 0,
+ * ldY < n, an option out of range), CHEM_EHIP, CHEM_ENOMEM, CHEM_ENONDET.
+ * Asynchronous on `stream` unless ckpt_out is given. */
 int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const double* P,
                    const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
                    double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
@@ -131,16 +167,21 @@ int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const dou
                    hipStream_t stream);
 
 /* Discrete adjoint of the checkpointed integration: reverse sweep over every
- * cell's accepted steps with the step sizes frozen.
+ * cell's accepted steps with the step sizes frozen, through the stages of the
+ * transformed Rosenbrock step of Sec. 2.3 (ROS4), the state conversion of
+ * eq. (conc_form1) and the source terms of eq. (dphidt).  (The paper does not
+ * differentiate the integration; this is the discrete adjoint of the method
+ * it uses.)
  *   gT[n], gY[K][ldY]   dL/dT_final, dL/dY_final (device)
  *   g_lnA               [Nr] dL/d ln A summed over cells (per_cell = 0) or
  *                       [Nr][n] per cell (per_cell = 1), overwritten
  *   gT0[n], gY0[K][ldY] nullable: dL/dT_in, dL/dY_in
  * One wavefront per cell: needs N <= 64 and the per-cell LDS (two N x (N+1)
  * matrices, dual vectors and Nr accumulators) within the device's LDS per
- * work-group (160 KiB on MI355X), else CHEM_EUNSUPPORTED.  The sum over
- * cells is taken in a fixed order.
- * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM, CHEM_EUNSUPPORTED. */
+ * work-group (160 KiB on MI355X), and a checkpoint taken with ROS4, else
+ * CHEM_EUNSUPPORTED.  The sum over cells is taken in a fixed order.
+ * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM, CHEM_EUNSUPPORTED.
+ * Synchronises the stream when per_cell = 0 (it frees the per-cell scratch). */
 int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, const double* gY,
                            int64_t ldY, double* g_lnA, int32_t per_cell, double* gT0,
                            double* gY0, hipStream_t stream);

@@ -72,10 +72,13 @@ def _ratio(T, Y, ref):
     return np.maximum(np.abs(T - ref["T"]) / barT, (np.abs(Y - ref["Y"]) / barY).max(0))
 
 
-def check(Tg, Yg, ng, ref, var, label, steps=True):
+def check(Tg, Yg, ng, ref, var, label, steps=True, worst=None, worst_n=None):
     """Apply R1-R3 (and S1, S2 when ``steps``) to GPU results against the
     oracle's ``ref`` and its rounding variants ``var`` (all on the same
-    cells).  Returns a short summary string."""
+    cells).  ``worst``/``worst_n`` replace the variants' counts of off-bar
+    cells and of cells with another step count when ``var`` covers only some
+    of the cells (a large batch: the counts then come from one variant run
+    over the whole batch).  Returns a short summary string."""
     barT = 1e-6 * np.abs(ref["T"])
     barY = 1e-6 * np.abs(ref["Y"]) + 1e-10
     envT = np.max([np.abs(v["T"] - ref["T"]) for v in var], axis=0)
@@ -83,7 +86,8 @@ def check(Tg, Yg, ng, ref, var, label, steps=True):
     sens_all = (envT > SENSITIVE * barT) | (envY > SENSITIVE * barY).any(0)
     rg = _ratio(Tg, Yg, ref)
     off = np.flatnonzero(rg > 1.0)
-    worst = max(int((_ratio(v["T"], v["Y"], ref) > 1.0).sum()) for v in var)
+    if worst is None:
+        worst = max(int((_ratio(v["T"], v["Y"], ref) > 1.0).sum()) for v in var)
     assert off.size <= 2 * worst + 2, "%s: %d cells off the bar, a rounding variant puts %d off (first %s)" % (
         label, off.size, worst, off[:5])
     sens = sens_all[off]
@@ -100,7 +104,8 @@ def check(Tg, Yg, ng, ref, var, label, steps=True):
         no = ref["n_acc"].astype(np.int64)
         d = np.abs(ng.astype(np.int64) - no)
         vn = np.array([v["n_acc"] for v in var], np.int64)
-        worst_n = int((vn != no).sum(1).max())
+        if worst_n is None:
+            worst_n = int((vn != no).sum(1).max())
         assert (d > 0).sum() <= 2 * worst_n + 2, "%s: steps differ on %d cells, a rounding variant on %d" % (
             label, (d > 0).sum(), worst_n)
         lim = np.where(sens_all, np.maximum(2, np.ceil(STEP_SPREAD * no)), 2)
@@ -109,3 +114,24 @@ def check(Tg, Yg, ng, ref, var, label, steps=True):
             label, bad, ng[bad], no[bad])
         msg += ", steps differ on %d (variants: up to %d)" % ((d > 0).sum(), worst_n)
     return msg
+
+
+def check_batch(o, T, P, Y, dt, Tg, Yg, ng, label, h=None, steps=True, **kw):
+    """The rule on a whole batch: the oracle and its FMA-contracted twin run on
+    every cell (the twin's counts stand for the variants' in R3 and S1), and
+    the nine variants run on the cells that are off the bar or whose step
+    count differs."""
+    ref = o.integrate(T, P, Y, dt, h=None if h is None else h.copy(), **kw)
+    fma = fma_twin(o).integrate(T, P, Y, dt, h=None if h is None else h.copy(), **kw)
+    worst = int((_ratio(fma["T"], fma["Y"], ref) > 1.0).sum())
+    worst_n = int((fma["n_acc"] != ref["n_acc"]).sum())
+    rg = _ratio(Tg, Yg, ref)
+    sel = np.flatnonzero((rg > 1.0) | (ng != ref["n_acc"]))
+    if sel.size == 0:
+        return ref, "%s: %d cells, none off the bar, equal step counts" % (label, T.size)
+    sub = lambda r: {k: (v[..., sel] if isinstance(v, np.ndarray) and v.shape[-1] == T.size else v)
+                     for k, v in r.items()}
+    var = variants(o, T[sel], P[sel], Y[:, sel], dt, h=None if h is None else h[sel], **kw)
+    msg = check(Tg[sel], Yg[:, sel], ng[sel], sub(ref), var, label, steps=steps, worst=worst,
+                worst_n=worst_n)
+    return ref, msg + " (of %d cells; rounding variants on the %d that differ)" % (T.size, sel.size)

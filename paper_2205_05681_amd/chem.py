@@ -16,9 +16,11 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchem.so")
 
-OK, EINVAL, EPARSE, EHIP, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+OK, EINVAL, EPARSE, EHIP, ENOMEM, EUNSUPPORTED, ENONDET = 0, -1, -2, -3, -4, -5, -6
 MODE_AUTO, MODE_PLAIN, MODE_PERSISTENT, MODE_TEAM, MODE_TEAM_PERSISTENT = 0, 1, 2, 3, 4
 MODES = {"auto": 0, "plain": 1, "persistent": 2, "team": 3, "team_persistent": 4}
+METHODS = {"ros4": 0, "ros3": 1, "rodas3": 2, "rodas4": 3}
+ESTIMATORS = {"embedded": 0, "filtered": 1}
 CELL_OK, CELL_MAX_STEPS, CELL_H_MIN, CELL_NONFINITE, CELL_SINGULAR = 0, 1, 2, 3, 4
 
 
@@ -33,6 +35,7 @@ class Opts(C.Structure):
                 ("safety", C.c_double), ("fac_min", C.c_double), ("fac_max", C.c_double),
                 ("T_cut", C.c_double), ("max_steps", C.c_int32), ("mode", C.c_int32),
                 ("wg_size", C.c_int32), ("waves_per_cu", C.c_int32), ("order", C.c_int32),
+                ("method", C.c_int32), ("estimator", C.c_int32), ("team_waves", C.c_int32),
                 ("stats", C.c_void_p)]
 
 
@@ -117,6 +120,10 @@ def default_opts(**kw):
     for k, v in kw.items():
         if k == "mode" and isinstance(v, str):
             v = MODES[v]
+        if k == "method" and isinstance(v, str):
+            v = METHODS[v]
+        if k == "estimator" and isinstance(v, str):
+            v = ESTIMATORS[v]
         if k == "stats":
             # a (3,) int64 device tensor that the call adds attempts/accepted/rejected to
             v = _ptr(v, "stats", torch.int64, (3,))
@@ -237,12 +244,14 @@ def adjoint(mech, ckpt, gT, gY, per_cell=False, initial=True):
 
 
 class IntegrateFn(torch.autograd.Function):
-    """(T1, Y1) = integrate(T, P, Y; lnA) as a differentiable function of T, Y
-    and lnA.  The backward pass is the library's discrete adjoint over the
-    checkpointed accepted steps (step sizes frozen)."""
+    """(T1, Y1) = IntegrateFn.apply(T, P, Y, lnA, dt, rtol, atol, mech[, opts]):
+    the integration as a differentiable function of T, Y and lnA (P, dt and
+    the tolerances are constants).  The backward pass is the library's
+    discrete adjoint over the checkpointed accepted steps (step sizes
+    frozen)."""
 
     @staticmethod
-    def forward(ctx, T, P, Y, lnA, mech, dt, rtol=1e-6, atol=1e-10, opts=None):
+    def forward(ctx, T, P, Y, lnA, dt, rtol, atol, mech, opts=None):
         T1, Y1, _, _, _, ck = integrate(mech, T.detach().contiguous(), P.detach().contiguous(),
                                         Y.detach().contiguous(), dt, rtol, atol,
                                         lnA=lnA.detach().contiguous(), opts=opts, checkpoint=True)

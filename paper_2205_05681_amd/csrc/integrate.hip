@@ -1,16 +1,18 @@
-// Batched ROS4 integration, one cell per thread (plain and persistent launch)
-// and the C ABI that drives it.
+// Batched Rosenbrock integration (ROS4 by default; ROS3, RODAS3, RODAS4), one
+// cell per thread (plain and persistent launch) or one wavefront per cell, and
+// the C ABI that drives them.
 //
-// Method (paper Sec. 2.3, transformed Rosenbrock form; Table T:solvers, ROS4):
+// Method (paper Sec. 2.3, transformed Rosenbrock form; Table T:solvers):
 //   M = I/(h gamma) - J(Phi_n), one LU per step;
-//   M u_i = f(Phi_n + sum_{j<i} a_ij u_j) + sum_{j<i} (c_ij / h) u_j, i = 1..4,
-//   with a_4j = a_3j so the fourth stage reuses the third f;
-//   Phi_{n+1} = Phi_n + sum m_j u_j, error estimate sum e_j u_j.
+//   M u_i = f(Phi_n + sum_{j<i} a_ij u_j) + sum_{j<i} (c_ij / h) u_j, i = 1..s,
+//   a stage whose argument equals the previous stage's reusing its f;
+//   Phi_{n+1} = Phi_n + sum m_j u_j, error estimate sum e_j u_j (optionally
+//   filtered by (I - h gamma J)^-1 = M^-1 / (h gamma)).
 // Step control (Sec. 3.1 tolerances; constants are this library's reading):
 //   err = RMS_i(err_i / (atol + rtol max(|Phi_n,i|, |Phi_n+1,i|)));
-//   accept if err <= 1; h <- h clamp(0.9 err^(-1/4), 0.2, 6), no growth right
-//   after a rejection; the last step is clipped to the remaining time; the
-//   final proposal is returned for reuse (Sec. 2.4.1).
+//   accept if err <= 1; h <- h clamp(0.9 err^(-1/elo), 0.2, 6), no growth
+//   right after a rejection; the last step is clipped to the remaining time;
+//   the final proposal is returned for reuse (Sec. 2.4.1).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +31,7 @@
 #include "../../include/chem.h"
 #include "kinetics.h"
 #include "mech.h"
-#include "ros4.h"
+#include "methods.h"
 #include "team.h"
 #include "adjoint.h"
 
@@ -46,6 +48,8 @@ struct IntParams {
   double* Y_out;
   double dt, rtol, atol, h_min, safety, fac_min, fac_max, T_cut;
   int32_t max_steps;
+  int32_t estimator;           // CHEM_EST_*
+  RosTable tab;                // the method's coefficients
   double* h_io;
   int32_t* n_steps;
   int32_t* status;
@@ -167,8 +171,7 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
   int32_t* piv = p.piv + slot;
   Lane phi{base + L.phi() * ld, ld}, ynew{base + L.ynew() * ld, ld};
   Lane f1{base + L.f1() * ld, ld}, fs{base + L.fs() * ld, ld}, ys{base + L.ys() * ld, ld};
-  Lane u1{base + L.u(0) * ld, ld}, u2{base + L.u(1) * ld, ld}, u3{base + L.u(2) * ld, ld},
-      u4{base + L.u(3) * ld, ld};
+  auto u = [&](int i) { return Lane{base + (int64_t)L.u(i) * ld, ld}; };   // stage vectors
   Lane J{base + (int64_t)L.jac() * ld, ld}, A{base + (int64_t)L.lu() * ld, ld};
   Lane conc{base + L.conc() * ld, ld}, wdot{base + L.wdot() * ld, ld};
   Lane hrt{base + L.hrt() * ld, ld}, cpr{base + L.cpr() * ld, ld}, gib{base + L.gibbs() * ld, ld};
@@ -234,33 +237,52 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
         eval_rhs_jac(M, P, phi, f1, J, L, base, ld, p.lnA);
         need_jac = false;
       }
-      const double d = 1.0 / (hs * ROS4_GAMMA);
+      const RosTable& R = p.tab;
+      const double d = 1.0 / (hs * R.gamma);
       for (int i = 0; i < N; ++i)
         for (int j = 0; j < N; ++j) A[i * N + j] = (i == j ? d : 0.0) - J[i * N + j];
       const int rc = lu_factor(A, piv, ld, N);
       double err = 0.0;
       if (rc == 0) {
-        const double ih = 1.0 / hs;
-        for (int i = 0; i < N; ++i) u1[i] = f1[i];
-        lu_solve(A, piv, ld, N, u1);
-        for (int i = 0; i < N; ++i) ys[i] = phi[i] + ROS4_A21 * u1[i];
-        eval_rhs(M, P, ys, fs, conc, wdot, hrt, cpr, gib, p.lnA);
-        for (int i = 0; i < N; ++i) u2[i] = fs[i] + (ROS4_C21 * ih) * u1[i];
-        lu_solve(A, piv, ld, N, u2);
-        for (int i = 0; i < N; ++i) ys[i] = phi[i] + ROS4_A31 * u1[i] + ROS4_A32 * u2[i];
-        eval_rhs(M, P, ys, fs, conc, wdot, hrt, cpr, gib, p.lnA);
-        for (int i = 0; i < N; ++i) u3[i] = fs[i] + (ROS4_C31 * u1[i] + ROS4_C32 * u2[i]) * ih;
-        lu_solve(A, piv, ld, N, u3);
-        for (int i = 0; i < N; ++i)
-          u4[i] = fs[i] + (ROS4_C41 * u1[i] + ROS4_C42 * u2[i] + ROS4_C43 * u3[i]) * ih;
-        lu_solve(A, piv, ld, N, u4);
-        for (int i = 0; i < N; ++i) {
-          const double y0 = phi[i];
-          const double yn = y0 + ROS4_M1 * u1[i] + ROS4_M2 * u2[i] + ROS4_M3 * u3[i] + ROS4_M4 * u4[i];
-          const double e = ROS4_E1 * u1[i] + ROS4_E2 * u2[i] + ROS4_E3 * u3[i] + ROS4_E4 * u4[i];
-          ynew[i] = yn;
-          const double sc = p.atol + p.rtol * fmax(fabs(y0), fabs(yn));
-          const double r = e / sc;
+        // stage i: f at phi + sum_{j<i} a_ij u_j (or the previous stage's f
+        // when the argument is the same), then M u_i = f + sum_{j<i} (c_ij/h) u_j
+        for (int i = 0; i < R.s; ++i) {
+          Lane ui = u(i);
+          if (i == 0) {
+            for (int k = 0; k < N; ++k) fs[k] = f1[k];
+          } else if (R.newf[i]) {
+            for (int k = 0; k < N; ++k) {
+              double y = phi[k];
+              for (int j = 0; j < i; ++j) y += R.a[i][j] * u(j)[k];
+              ys[k] = y;
+            }
+            eval_rhs(M, P, ys, fs, conc, wdot, hrt, cpr, gib, p.lnA);
+          }
+          for (int k = 0; k < N; ++k) {
+            double r = fs[k];
+            for (int j = 0; j < i; ++j) r += (R.c[i][j] / hs) * u(j)[k];
+            ui[k] = r;
+          }
+          lu_solve(A, piv, ld, N, ui);
+        }
+        // new state and error estimate (into ys; filtered in place if asked)
+        for (int k = 0; k < N; ++k) {
+          double yn = phi[k], e = 0.0;
+          for (int j = 0; j < R.s; ++j) {
+            const double uj = u(j)[k];
+            yn += R.m[j] * uj;
+            e += R.e[j] * uj;
+          }
+          ynew[k] = yn;
+          ys[k] = e;
+        }
+        if (p.estimator == CHEM_EST_FILTERED) {
+          lu_solve(A, piv, ld, N, ys);
+          for (int k = 0; k < N; ++k) ys[k] = ys[k] / (hs * R.gamma);
+        }
+        for (int k = 0; k < N; ++k) {
+          const double sc = p.atol + p.rtol * fmax(fabs(phi[k]), fabs(ynew[k]));
+          const double r = ys[k] / sc;
           err += r * r;
         }
         err = sqrt(err / N);
@@ -275,7 +297,7 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
         }
       } else {
         bad = 0;
-        double fac = (err > 0.0) ? p.safety * pow(err, -0.25) : p.fac_max;
+        double fac = (err > 0.0) ? p.safety * pow(err, -1.0 / p.tab.elo) : p.fac_max;
         if (err <= 1.0) {
           // (a record slot exists for every step the counting pass saw)
           if (p.ck_data && ck_rec + accepted < p.ck_off[cell + 1] - 1) {
@@ -381,20 +403,37 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       // factors of M = I/(h gamma) - J over J
       int perm;
       double rdiag;
-      const int rc = team_lu<NMAX>(L.J, ldj, N, 1.0 / (hs * ROS4_GAMMA), perm, rdiag);
+      const RosTable& R = p.tab;
+      const int rc = team_lu<NMAX>(L.J, ldj, N, 1.0 / (hs * R.gamma), perm, rdiag);
       double err = 0.0, ynew = 0.0;
       if (rc == 0) {
-        const double ih = 1.0 / hs;
         const double* F = L.J;
-        const double u1 = team_solve<NMAX>(F, ldj, N, perm, rdiag, f1);
-        double fs = team_rhs(M, P, phi + ROS4_A21 * u1, L, p.lnA);
-        const double u2 = team_solve<NMAX>(F, ldj, N, perm, rdiag, fs + (ROS4_C21 * ih) * u1);
-        fs = team_rhs(M, P, phi + ROS4_A31 * u1 + ROS4_A32 * u2, L, p.lnA);
-        const double u3 = team_solve<NMAX>(F, ldj, N, perm, rdiag, fs + (ROS4_C31 * u1 + ROS4_C32 * u2) * ih);
-        const double u4 = team_solve<NMAX>(F, ldj, N, perm, rdiag,
-                                           fs + (ROS4_C41 * u1 + ROS4_C42 * u2 + ROS4_C43 * u3) * ih);
-        ynew = phi + ROS4_M1 * u1 + ROS4_M2 * u2 + ROS4_M3 * u3 + ROS4_M4 * u4;
-        const double e = ROS4_E1 * u1 + ROS4_E2 * u2 + ROS4_E3 * u3 + ROS4_E4 * u4;
+        // stage i: f at phi + sum_{j<i} a_ij u_j (or the previous stage's f
+        // when the argument is the same), then M u_i = f + sum_{j<i} (c_ij/h)
+        // u_j.  Lane i keeps element i of every stage vector in the LDS stage
+        // area (a per-lane array indexed by the stage, read back by the same
+        // lane only, so no barrier is needed).
+        double fs = f1;
+#pragma unroll 1
+        for (int i = 0; i < R.s; ++i) {
+          if (i > 0 && R.newf[i]) {
+            double y = phi;
+            for (int j = 0; j < i; ++j) y += R.a[i][j] * L.ust[64 * j + lane];
+            fs = team_rhs(M, P, y, L, p.lnA);
+          }
+          double r = fs;
+          for (int j = 0; j < i; ++j) r += (R.c[i][j] / hs) * L.ust[64 * j + lane];
+          L.ust[64 * i + lane] = team_solve<NMAX>(F, ldj, N, perm, rdiag, r);
+        }
+        double e = 0.0;
+        ynew = phi;
+        for (int j = 0; j < R.s; ++j) {
+          const double uj = L.ust[64 * j + lane];
+          ynew += R.m[j] * uj;
+          e += R.e[j] * uj;
+        }
+        if (p.estimator == CHEM_EST_FILTERED)
+          e = team_solve<NMAX>(F, ldj, N, perm, rdiag, e) / (hs * R.gamma);
         const double sc = p.atol + p.rtol * fmax(fabs(phi), fabs(ynew));
         const double r = (lane < N) ? e / sc : 0.0;
         err = sqrt(wave_sum(r * r) / N);
@@ -409,7 +448,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
         continue;
       }
       bad = 0;
-      double fac = (err > 0.0) ? p.safety * pow(err, -0.25) : p.fac_max;
+      double fac = (err > 0.0) ? p.safety * pow(err, -1.0 / p.tab.elo) : p.fac_max;
       if (err <= 1.0) {
         // (a record slot exists for every step the counting pass saw)
         if (p.ck_data && ck_rec + accepted < p.ck_off[cell + 1] - 1) {
@@ -771,6 +810,7 @@ struct chem_graph_s {
 
 struct chem_ckpt_s {
   chem_mech_t mech = nullptr;
+  int32_t method = CHEM_METHOD_ROS4;
   hipStream_t stream = nullptr;
   int64_t n = 0;
   double* data = nullptr;        // per cell: (Phi_n, h_n) of every accepted step, then the final Phi
@@ -908,6 +948,9 @@ void chem_opts_default(chem_opts* o) {
   o->wg_size = 0;
   o->waves_per_cu = 0;
   o->order = CHEM_ORDER_HOT_FIRST;
+  o->method = CHEM_METHOD_ROS4;
+  o->estimator = CHEM_EST_EMBEDDED;
+  o->team_waves = 0;
   o->stats = nullptr;
 }
 
@@ -918,7 +961,8 @@ const char* chem_error_string(int code) {
     case CHEM_EPARSE: return "mechanism parse error";
     case CHEM_EHIP: return "HIP runtime error";
     case CHEM_ENOMEM: return "device out of memory";
-    case CHEM_EUNSUPPORTED: return "mechanism exceeds compiled limits";
+    case CHEM_EUNSUPPORTED: return "mechanism exceeds compiled limits, or method not supported here";
+    case CHEM_ENONDET: return "checkpointed integration: the recording pass did not repeat the counted steps";
     default: return "unknown error";
   }
 }
@@ -1033,7 +1077,25 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
                           const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
                           double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
                           const double* lnA, const chem_opts* opts, double* ck_data,
-                          const int64_t* ck_off, hipStream_t stream);
+                          const int64_t* ck_off, int32_t* ck_count, hipStream_t stream);
+
+// The options a call runs with: the caller's (or the defaults), with the
+// autotuner's choice for this batch size in place of CHEM_MODE_AUTO.
+static int resolve_opts(chem_mech_t m, int64_t n, const chem_opts* opts, chem_opts* out) {
+  chem_opts o;
+  chem_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.mode == CHEM_MODE_AUTO) {
+    chem_opts t;
+    if (tuned_lookup(m, n, &t)) {
+      o.mode = t.mode;
+      o.wg_size = t.wg_size;
+      o.waves_per_cu = t.waves_per_cu;
+    }
+  }
+  *out = o;
+  return CHEM_OK;
+}
 
 int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P, const double* Y_in,
                    int64_t ldY, double* T_out, double* Y_out, double dt, double rtol, double atol,
@@ -1041,7 +1103,7 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
                    const chem_opts* opts, chem_ckpt_t* ckpt_out, hipStream_t stream) {
   if (!ckpt_out)
     return integrate_impl(m, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
-                          status, lnA, opts, nullptr, nullptr, stream);
+                          status, lnA, opts, nullptr, nullptr, nullptr, stream);
   *ckpt_out = nullptr;
   if (!m || n <= 0 || !T_in || !P || !Y_in || !T_out || !Y_out || ldY < n) return CHEM_EINVAL;
   HIPCHECK(hipSetDevice(m->device));
@@ -1081,8 +1143,14 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   } else if (hipMemsetAsync(th, 0, n * 8, stream)) {
     return fail(CHEM_EHIP);
   }
-  int rc = integrate_impl(m, n, c->T0, c->P, c->Y0, n, tT, tY, dt, rtol, atol, th, tn, nullptr,
-                          c->lnA, opts, nullptr, nullptr, stream);
+  // both passes run the same resolved options (an autotuner update between
+  // them must not change the launch, which could change the rounding)
+  chem_opts ro;
+  int rc = resolve_opts(m, n, opts, &ro);
+  if (rc) return fail(rc);
+  c->method = ro.method;
+  rc = integrate_impl(m, n, c->T0, c->P, c->Y0, n, tT, tY, dt, rtol, atol, th, tn, nullptr,
+                      c->lnA, &ro, nullptr, nullptr, nullptr, stream);
   if (rc) return fail(rc);
   std::vector<int32_t> steps(n);
   if (hipMemcpyAsync(steps.data(), tn, n * 4, hipMemcpyDeviceToHost, stream) ||
@@ -1112,9 +1180,14 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
     return fail(CHEM_EHIP);
   }
   rc = integrate_impl(m, n, c->T0, c->P, c->Y0, n, T_out, Y_out, dt, rtol, atol, h2, n_steps, status,
-                      c->lnA, opts, c->data, c->off, stream);
+                      c->lnA, &ro, c->data, c->off, tn, stream);
   if (rc) return fail(rc);
-  if (hipStreamSynchronize(stream)) return fail(CHEM_EHIP);
+  // pass 2 must have taken exactly the steps pass 1 counted
+  std::vector<int32_t> steps2(n);
+  if (hipMemcpyAsync(steps2.data(), tn, n * 4, hipMemcpyDeviceToHost, stream) ||
+      hipStreamSynchronize(stream))
+    return fail(CHEM_EHIP);
+  if (steps2 != steps) return fail(CHEM_ENONDET);
   (void)hipFree(tT);
   (void)hipFree(tY);
   (void)hipFree(th);
@@ -1149,28 +1222,22 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
                           const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
                           double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
                           const double* lnA, const chem_opts* opts, double* ck_data,
-                          const int64_t* ck_off, hipStream_t stream) {
+                          const int64_t* ck_off, int32_t* ck_count, hipStream_t stream) {
 
   if (!m || n < 0 || n > INT32_MAX) return CHEM_EINVAL;
   if (n > 0 && (!T_in || !P || !Y_in || !T_out || !Y_out)) return CHEM_EINVAL;
   if (!(dt > 0) || !(rtol > 0) || !(atol >= 0) || ldY < n) return CHEM_EINVAL;
   chem_opts o;
-  chem_opts_default(&o);
-  if (opts) o = *opts;
+  resolve_opts(m, n, opts, &o);
   if (o.mode < CHEM_MODE_AUTO || o.mode > CHEM_MODE_TEAM_PERSISTENT) return CHEM_EINVAL;
   if (o.wg_size < 0 || o.wg_size > 256 || (o.wg_size % 64) != 0) return CHEM_EINVAL;
   if (o.max_steps <= 0 || !(o.fac_min > 0) || !(o.fac_max >= 1) || !(o.safety > 0)) return CHEM_EINVAL;
   if (o.order != CHEM_ORDER_INDEX && o.order != CHEM_ORDER_HOT_FIRST) return CHEM_EINVAL;
+  if (o.method < 0 || o.method >= N_METHODS) return CHEM_EINVAL;
+  if (o.estimator != CHEM_EST_EMBEDDED && o.estimator != CHEM_EST_FILTERED) return CHEM_EINVAL;
+  if (o.team_waves != 0 && o.team_waves != 1) return CHEM_EINVAL;
   if (n == 0) return CHEM_OK;
   HIPCHECK(hipSetDevice(m->device));
-  if (o.mode == CHEM_MODE_AUTO) {
-    chem_opts t;
-    if (tuned_lookup(m, n, &t)) {
-      o.mode = t.mode;
-      o.wg_size = t.wg_size;
-      o.waves_per_cu = t.waves_per_cu;
-    }
-  }
   int mode = o.mode;
   if (mode == CHEM_MODE_AUTO) mode = (m->view.N <= 64) ? CHEM_MODE_TEAM_PERSISTENT : CHEM_MODE_PERSISTENT;
   // one wavefront per cell needs N <= 64; larger mechanisms use one cell per thread
@@ -1205,6 +1272,8 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
     p.fac_max = o.fac_max;
     p.T_cut = o.T_cut;
     p.max_steps = o.max_steps;
+    p.estimator = o.estimator;
+    p.tab = TABLES[o.method];
     p.h_io = h_io;
     p.n_steps = n_steps;
     p.status = status;
@@ -1213,6 +1282,7 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
     p.stats = o.stats;
     p.ck_data = ck_data;
     p.ck_off = ck_off;
+    p.ck_count = ck_count;
     TeamKernel kern = team_kernel(m->view.N);
     const size_t lds = TeamLds::doubles(m->view.N) * sizeof(double);
     unsigned grid = (unsigned)n;
@@ -1272,6 +1342,8 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
   p.fac_max = o.fac_max;
   p.T_cut = o.T_cut;
   p.max_steps = o.max_steps;
+  p.estimator = o.estimator;
+  p.tab = TABLES[o.method];
   p.h_io = h_io;
   p.n_steps = n_steps;
   p.status = status;
@@ -1283,7 +1355,7 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
   p.stats = o.stats;
   p.ck_data = ck_data;
   p.ck_off = ck_off;
-  p.ck_count = nullptr;
+  p.ck_count = ck_count;
   const unsigned grid = (unsigned)(slots / wg);
   if (persistent) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, w->queue);
@@ -1301,7 +1373,7 @@ int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, co
   if (!m || !ckpt || ckpt->mech != m || !gT || !gY || !g_lnA || ldY < ckpt->n) return CHEM_EINVAL;
   const int N = m->view.N, Nr = m->view.Nr;
   const int64_t n = ckpt->n;
-  if (N > 64) return CHEM_EUNSUPPORTED;
+  if (N > 64 || ckpt->method != CHEM_METHOD_ROS4) return CHEM_EUNSUPPORTED;
   const size_t lds = (2 * (size_t)N * (N + 1) + 2 * TeamLdsT<double>::vec_elems(N) + 32 + Nr) * 8;
   HIPCHECK(hipSetDevice(m->device));
   int lds_max = 0;
@@ -1412,7 +1484,7 @@ int chem_autotune(chem_mech_t m, int64_t n, const double* T_in, const double* P,
     for (int rep = 0; rep < 3 && rc == CHEM_OK; ++rep) {
       (void)hipEventRecord(e0, stream);
       rc = integrate_impl(m, ns, Ts, Ps, Ys, ns, To, Yo, dt, rtol, atol, nullptr, nullptr, nullptr,
-                          nullptr, &cand[i], nullptr, nullptr, stream);
+                          nullptr, &cand[i], nullptr, nullptr, nullptr, stream);
       (void)hipEventRecord(e1, stream);
       float t = 0;
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
@@ -1467,7 +1539,7 @@ int chem_graph_create(chem_mech_t m, int64_t n, const double* T_in, const double
     return CHEM_EHIP;
   }
   const int rc = integrate_impl(m, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
-                                status, lnA, opts, nullptr, nullptr, g->stream);
+                                status, lnA, opts, nullptr, nullptr, nullptr, g->stream);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(g->stream, &graph);
   if (rc || e != hipSuccess || !graph) {

@@ -88,21 +88,21 @@ struct WsLayout {
   __host__ __device__ int ynew() const { return N; }
   __host__ __device__ int f1() const { return 2 * N; }
   __host__ __device__ int fs() const { return 3 * N; }
-  __host__ __device__ int u(int i) const { return (4 + i) * N; }      // i = 0..3
-  __host__ __device__ int ys() const { return 8 * N; }
-  __host__ __device__ int ah() const { return 9 * N; }
-  __host__ __device__ int aw() const { return 10 * N; }
-  __host__ __device__ int br() const { return 11 * N; }
-  __host__ __device__ int conc() const { return 12 * N; }
-  __host__ __device__ int wdot() const { return 12 * N + K; }
-  __host__ __device__ int hrt() const { return 12 * N + 2 * K; }
-  __host__ __device__ int cpr() const { return 12 * N + 3 * K; }
-  __host__ __device__ int gibbs() const { return 12 * N + 4 * K; }
-  __host__ __device__ int gb() const { return 12 * N + 5 * K; }
-  __host__ __device__ int tb() const { return 12 * N + 6 * K; }
-  __host__ __device__ int jac() const { return 12 * N + 7 * K; }
-  __host__ __device__ int lu() const { return 12 * N + 7 * K + N * N; }
-  __host__ __device__ int total() const { return 12 * N + 7 * K + 2 * N * N; }
+  __host__ __device__ int u(int i) const { return (4 + i) * N; }      // i = 0..5 (stages)
+  __host__ __device__ int ys() const { return 10 * N; }
+  __host__ __device__ int ah() const { return 11 * N; }
+  __host__ __device__ int aw() const { return 12 * N; }
+  __host__ __device__ int br() const { return 13 * N; }
+  __host__ __device__ int conc() const { return 14 * N; }
+  __host__ __device__ int wdot() const { return 14 * N + K; }
+  __host__ __device__ int hrt() const { return 14 * N + 2 * K; }
+  __host__ __device__ int cpr() const { return 14 * N + 3 * K; }
+  __host__ __device__ int gibbs() const { return 14 * N + 4 * K; }
+  __host__ __device__ int gb() const { return 14 * N + 5 * K; }
+  __host__ __device__ int tb() const { return 14 * N + 6 * K; }
+  __host__ __device__ int jac() const { return 14 * N + 7 * K; }
+  __host__ __device__ int lu() const { return 14 * N + 7 * K + N * N; }
+  __host__ __device__ int total() const { return 14 * N + 7 * K + 2 * N * N; }
 };
 
 // NASA-7 thermo of every species at T: hRT, cpR and g = s/R - h/(RT) into the

@@ -1,8 +1,9 @@
 // One wavefront per cell ("team" kernels).
 //
 // Layout inside a wavefront (64 lanes, N = K + 1 <= 64):
-//   * element i of every state-sized vector (Phi, f, u_1..u_4, ...) lives in
-//     lane i, one register each;
+//   * element i of every state-sized vector (Phi, f, ...) lives in lane i, one
+//     register each; the stage vectors u_1..u_s of the integrator sit in a
+//     small LDS area, each lane holding (and reading back) its own element;
 //   * reactions are spread over lanes (reaction j on lane j mod 64); their
 //     contributions to the production rates and to the Jacobian are scattered
 //     into LDS with FP64 LDS atomics, then the chain rule through C(Phi) is
@@ -20,7 +21,7 @@
 
 #include "kinetics.h"
 #include "mech.h"
-#include "ros4.h"
+#include "methods.h"
 
 namespace chem {
 
@@ -95,15 +96,17 @@ struct TeamLdsT {
   S* dwdT;   // [64]
   S* dwdV;   // [64]
   S* vec;    // [64]       staging of a lane-distributed vector
+  S* ust;    // [MAX_STAGES][64] stage vectors of the integrator (bind() layout only)
   int* plane;            // [64]
-  // Two layouts.  bind(): dwdT and dwdV first, then the matrix, brow and the
-  // other vectors, one block of doubles(N) doubles whose last 32 hold plane.
+  // Two layouts.  bind(): dwdT and dwdV first, then the matrix, brow, the
+  // other vectors and the stage area, one block of doubles(N) doubles whose
+  // last 32 hold plane.
   // bind2(): the matrix at Jb and brow plus every vector at Vb (the adjoint's
   // two matrix views share one vector block).
   // Elements of S besides the matrix: brow and ten 64-entry vectors.
   static __host__ __device__ size_t vec_elems(int N) { return (size_t)(N + 1) + 10 * 64; }
   static __host__ __device__ size_t doubles(int N) {
-    return ((size_t)N * (N + 1) + vec_elems(N)) * (sizeof(S) / sizeof(double)) + 32;
+    return ((size_t)N * (N + 1) + vec_elems(N) + MAX_STAGES * 64) * (sizeof(S) / sizeof(double)) + 32;
   }
   __device__ void bind2(S* Jb, S* Vb, int* pl, int N) {
     J = Jb;
@@ -118,6 +121,7 @@ struct TeamLdsT {
     dwdT = tb + 64;
     dwdV = dwdT + 64;
     vec = dwdV + 64;
+    ust = nullptr;
     plane = pl;
   }
   __device__ void bind(double* base, int N) {
@@ -134,6 +138,7 @@ struct TeamLdsT {
     gb = wdot + 64;
     tb = gb + 64;
     vec = tb + 64;
+    ust = vec + 64;
     plane = (int*)(base + doubles(N) - 32);
   }
 };

@@ -5,16 +5,23 @@ what the method needs, independent of how a kernel organises it.  Additions,
 subtractions, multiplications and divisions count 1, a fused multiply-add 2;
 exp/log/log10 are counted separately (they are not part of the flop count).
 
-Per attempted step the method needs (paper Sec. 2.3, one LU per step):
+Per attempted step an s-stage method needs (paper Sec. 2.3, one LU per
+step):
   * M = I/(h gamma) - J and its LU with partial pivoting;
-  * four forward/backward substitutions;
-  * two new source-term evaluations (stages 2 and 3; stage 4 reuses 3);
+  * s forward/backward substitutions (one more for the filtered estimate);
+  * the new source-term evaluations of stages 2..s (a stage whose argument
+    equals the previous stage's reuses its f: ROS4 needs 2, ROS3 1, RODAS3 2,
+    RODAS4 5);
   * the stage combinations and the error norm.
 Per accepted step it also needs f and the analytical Jacobian at the new
 state; a rejected step reuses them.  So for a batch:
-  flops = accepted * F_fJ + attempts * (F_M + F_LU + 4 F_sol + 2 F_f + F_vec).
+  flops = accepted * F_fJ + attempts * (F_M + F_LU + n_sol F_sol + n_f F_f + F_vec).
 """
+
 from __future__ import annotations
+
+# stages, new f evaluations per attempt (stage 1 uses the f evaluated with J)
+METHOD_SHAPE = {"ros4": (4, 2), "ros3": (3, 1), "rodas3": (4, 2), "rodas4": (6, 5)}
 
 
 def _thermo(K, with_dcp):
@@ -58,7 +65,7 @@ def _transcendentals(r):
     return t
 
 
-def step_counts(mech):
+def step_counts(mech, method="ros4", estimator="embedded"):
     """Dict of per-piece algorithmic flop counts for a synth.Mechanism."""
     K = mech.n_species
     N = K + 1
@@ -70,16 +77,20 @@ def step_counts(mech):
     f_m = N * N + 2
     f_lu = sum((N - k - 1) + 2 * (N - k - 1) ** 2 for k in range(N))
     f_sol = N * (N - 1) + N * (N - 1) + N
-    f_vec = 30 * N + 3 * N + 2
+    s, nf = METHOD_SHAPE[method]
+    n_sol = s + (1 if estimator == "filtered" else 0)
+    # stage arguments and right-hand sides (2 FMA per earlier stage each),
+    # the new state and the estimate (2 FMA per stage each), the error norm
+    f_vec = N * (2 * s * (s - 1) + 4 * s + 6) + 2
     t_rhs = sum(_transcendentals(r) for r in rx) + 2
     return dict(N=N, rhs=f_rhs, rhs_jac=f_fj, matrix=f_m, lu=f_lu, solve=f_sol, vector=f_vec,
-                per_attempt=f_m + f_lu + 4 * f_sol + 2 * f_rhs + f_vec, per_accept=f_fj,
-                transcendentals_per_rhs=t_rhs)
+                per_attempt=f_m + f_lu + n_sol * f_sol + nf * f_rhs + f_vec, per_accept=f_fj,
+                transcendentals_per_rhs=t_rhs, f_per_attempt=nf)
 
 
-def batch_flops(mech, attempts, accepted):
+def batch_flops(mech, attempts, accepted, method="ros4", estimator="embedded"):
     """Algorithmic FP64 flops and transcendental calls of a batch."""
-    c = step_counts(mech)
+    c = step_counts(mech, method, estimator)
     flops = accepted * c["per_accept"] + attempts * c["per_attempt"]
-    trans = (accepted + 2 * attempts) * c["transcendentals_per_rhs"]
+    trans = (accepted + c["f_per_attempt"] * attempts) * c["transcendentals_per_rhs"]
     return flops, trans

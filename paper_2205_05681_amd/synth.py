@@ -235,11 +235,14 @@ def _key(comp, elements):
 
 
 def generate_mechanism(n_species, n_reactions, n_third_body, n_falloff, troe, elements,
-                       max_c, seed, must_have=()):
+                       max_c, seed, must_have=(), core=()):
     """Draw an element-balanced reversible mechanism.
 
     n_falloff reactions are Troe if ``troe`` else Lindemann.  The last species
-    is N2 and is inert (collider only).
+    is N2 and is inert (collider only).  ``core`` lists reactions by species
+    names, ``(kind, reactants, products)``, that the mechanism must contain
+    (drawn first, with rate parameters from the same distributions as the
+    rest; they count towards n_reactions and the third-body/falloff totals).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     pool = _candidate_pool(elements, max_c, max_h=2 * max_c + 4 if max_c else 4,
@@ -300,12 +303,59 @@ def generate_mechanism(n_species, n_reactions, n_third_body, n_falloff, troe, el
     uses = np.zeros(active, int)
     kinds = ["T"] * n_third_body + ["F" if troe else "L"] * n_falloff
     kinds += ["E"] * (n_reactions - len(kinds))
+
+    def finish(kind, reac, prod, h):
+        """Rate parameters of a reaction oriented endothermic-forward (enthalpy h)."""
+        for x, _ in reac + prod:
+            uses[x] += 1
+        Ea = max(rng.uniform(0.0, 200.0), h)            # kJ/mol
+        theta = Ea * 1000.0 / R_J_MOL_K
+        b = rng.uniform(-1.5, 1.5)
+        A_cgs = 10.0 ** rng.uniform(8.0, 16.0)
+        ordr = order(reac) + (1 if kind == "T" else 0)
+        lnA = math.log(A_cgs) + (ordr - 1) * math.log(1e-3)
+        eff = []
+        low = None
+        tr = None
+        if kind != "E":
+            ne = int(rng.integers(0, 4))
+            for s_ in rng.choice(K, size=ne, replace=False):
+                eff.append((int(s_), float(rng.uniform(0.4, 6.0))))
+            eff.sort()
+        if kind in "LF":
+            A0_cgs = A_cgs * 10.0 ** rng.uniform(3.0, 7.0)
+            lnA0 = math.log(A0_cgs) + order(reac) * math.log(1e-3)
+            low = (lnA0, rng.uniform(-1.5, 1.5), rng.uniform(0.0, theta))
+        if kind == "F":
+            a = rng.uniform(0.1, 0.9)
+            T3 = math.exp(rng.uniform(math.log(30.0), math.log(1000.0)))
+            T1 = math.exp(rng.uniform(math.log(500.0), math.log(5000.0)))
+            T2 = math.exp(rng.uniform(math.log(1000.0), math.log(1e4))) if rng.random() < 0.5 else 0.0
+            tr = (a, T3, T1, T2)
+        reactions.append(Reaction(kind, list(reac), list(prod), lnA, b, theta, eff, low, tr))
+
+    names = [_formula(c) for c in chosen]
+    for kind, rs, ps in core:
+        if kind != "E":
+            kinds.remove("F" if (kind in "LF" and troe) else ("L" if kind in "LF" else "T"))
+        else:
+            kinds.remove("E")
+        side = lambda xs: tuple(sorted((names.index(_formula(_parse_formula(n_))), c_) for n_, c_ in
+                                       {n_: xs.count(n_) for n_ in xs}.items()))
+        reac, prod = side(rs), side(ps)
+        assert _key_sum(reac, keys) == _key_sum(prod, keys), (rs, ps)
+        kind = ("F" if troe else "L") if kind in "LF" else kind
+        seen.add((tuple(sorted(reac)), tuple(sorted(prod))))
+        h = dH(reac, prod)
+        if h < 0:
+            reac, prod, h = prod, reac, -h
+        finish(kind, reac, prod, h)
     attempts = 0
     while len(reactions) < n_reactions:
         attempts += 1
         if attempts > 200000:
             raise RuntimeError("could not draw enough reactions")
-        kind = kinds[len(reactions)]
+        kind = kinds[len(reactions) - len(core)]
         if kind == "E":
             # bimolecular exchange A + B = C + D, seeded from a rarely used species
             if rng.random() < 0.5:
@@ -346,36 +396,14 @@ def generate_mechanism(n_species, n_reactions, n_third_body, n_falloff, troe, el
         if h > (400.0 if kind == "E" else 600.0):
             continue
         seen.add(sig)
-        for x, _ in reac + prod:
-            uses[x] += 1
-        Ea = max(rng.uniform(0.0, 200.0), h)            # kJ/mol
-        theta = Ea * 1000.0 / R_J_MOL_K
-        b = rng.uniform(-1.5, 1.5)
-        A_cgs = 10.0 ** rng.uniform(8.0, 16.0)
-        ordr = order(reac) + (1 if kind == "T" else 0)
-        lnA = math.log(A_cgs) + (ordr - 1) * math.log(1e-3)
-        eff = []
-        low = None
-        tr = None
-        if kind != "E":
-            ne = int(rng.integers(0, 4))
-            for s_ in rng.choice(K, size=ne, replace=False):
-                eff.append((int(s_), float(rng.uniform(0.4, 6.0))))
-            eff.sort()
-        if kind in "LF":
-            A0_cgs = A_cgs * 10.0 ** rng.uniform(3.0, 7.0)
-            lnA0 = math.log(A0_cgs) + order(reac) * math.log(1e-3)
-            low = (lnA0, rng.uniform(-1.5, 1.5), rng.uniform(0.0, theta))
-        if kind == "F":
-            a = rng.uniform(0.1, 0.9)
-            T3 = math.exp(rng.uniform(math.log(30.0), math.log(1000.0)))
-            T1 = math.exp(rng.uniform(math.log(500.0), math.log(5000.0)))
-            T2 = math.exp(rng.uniform(math.log(1000.0), math.log(1e4))) if rng.random() < 0.5 else 0.0
-            tr = (a, T3, T1, T2)
-        reactions.append(Reaction(kind, list(reac), list(prod), lnA, b, theta, eff, low, tr))
+        finish(kind, reac, prod, h)
     order_ix = rng.permutation(len(reactions))
     reactions = [reactions[i] for i in order_ix]
     return Mechanism(list(elements), species, reactions)
+
+
+def _key_sum(side, keys):
+    return tuple(sum(nu * keys[i][e] for i, nu in side) for e in range(len(keys[0])))
 
 
 def _parse_formula(f):
@@ -413,10 +441,33 @@ def mech_ch4(seed=102):
                               must_have=CH4_MUST)
 
 
+# The fuel's own chemistry, present in every hydrocarbon mechanism: unimolecular
+# decomposition, hydrogen abstraction by O2 and by the radical pool, the
+# H + O2 branching step and the main oxidation path of the methyl radical.
+FUEL_CORE = (
+    ("F", ["CH4"], ["CH3", "H"]),
+    ("E", ["CH4", "O2"], ["CH3", "HO2"]),
+    ("E", ["CH4", "H"], ["CH3", "H2"]),
+    ("E", ["CH4", "O"], ["CH3", "OH"]),
+    ("E", ["CH4", "OH"], ["CH3", "H2O"]),
+    ("E", ["CH4", "HO2"], ["CH3", "H2O2"]),
+    ("E", ["H", "O2"], ["O", "OH"]),
+    ("E", ["CH3", "O2"], ["CH3O", "O"]),
+    ("E", ["CH3", "HO2"], ["CH3O", "OH"]),
+    ("E", ["CH2O", "OH"], ["CHO", "H2O"]),
+    ("E", ["CHO", "O2"], ["CO", "HO2"]),
+    ("E", ["CO", "OH"], ["CO2", "H"]),
+)
+
+
 def mech_large(seed=104):
-    """111 species (C, H, O, N; at most C4), 784 reactions: 60 third-body, 40 Troe."""
+    """111 species (C, H, O, N; at most C4), 784 reactions: 60 third-body, 40 Troe,
+    with the fuel core (FUEL_CORE).  Without it the draw for this seed holds a
+    single route out of the fuel/air mixture (CH4 (+M) = H2 + CH2, with a rate
+    constant five orders below the CH4-shaped mechanism's), and mixtures at
+    1,600 K take one step per 1e-5 s: chemically inert."""
     return generate_mechanism(111, 784, 60, 40, True, ["C", "H", "O", "N"], 4, seed,
-                              must_have=CH4_MUST)
+                              must_have=CH4_MUST, core=FUEL_CORE)
 
 
 def mech_n30(seed=106):

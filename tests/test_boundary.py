@@ -45,3 +45,17 @@ def test_mechanism_parse_errors_without_gpu(tmp_path):
     assert L.chem_mech_load(str(bad).encode(), 0, ctypes.byref(h)) == chem.EPARSE
     assert L.chem_mech_load(str(tmp_path / "missing.txt").encode(), 0, ctypes.byref(h)) == chem.EPARSE
     assert L.chem_mech_load(None, 0, ctypes.byref(h)) == chem.EINVAL
+
+
+def test_opts_struct_layout_matches_the_header():
+    """chem_opts_default writes exactly the Python Opts structure: nothing past
+    its end (a sentinel tail survives) and the last field, the stats pointer,
+    is set (to null)."""
+    from paper_2205_05681_amd import chem
+    size = ctypes.sizeof(chem.Opts)
+    buf = (ctypes.c_ubyte * (size + 64))(*([0xAB] * (size + 64)))
+    chem.lib().chem_opts_default(ctypes.cast(buf, ctypes.POINTER(chem.Opts)))
+    assert bytes(buf[size:]) == b"\xab" * 64
+    o = chem.Opts.from_buffer(buf)
+    assert o.stats is None
+    assert o.method == 0 and o.estimator == 0 and o.team_waves == 0 and o.order == 1

@@ -184,7 +184,7 @@ def test_autograd_function(chem, ch4, case):
     T = dev(case["T"]).requires_grad_(True)
     Y = dev(case["Y"]).requires_grad_(True)
     lnA = dev(o.lnA).requires_grad_(True)
-    T1, Y1 = chem.IntegrateFn.apply(T, dev(case["P"]), Y, lnA, mech, 1e-5)
+    T1, Y1 = chem.IntegrateFn.apply(T, dev(case["P"]), Y, lnA, 1e-5, 1e-6, 1e-10, mech)
     loss = (dev(case["w"])[:, None] * Y1).sum()
     loss.backward()
     torch.cuda.synchronize()

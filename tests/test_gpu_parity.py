@@ -2,12 +2,11 @@
 
 Bar, per cell: |T_gpu - T_or| <= 1e-6 T_or and |Y_gpu - Y_or| <= 1e-6 |Y_or|
 + 1e-10 (rtol 1e-6 on T and Y, atol 1e-10).  Both sides run the same
-algorithm and controller; they differ only in rounding (FMA contraction,
-summation order, device vs host exp/log).  Cells that take hundreds of steps
-through a thermal runaway amplify rounding differences: the oracle itself
-moves some of them past the bar when its input changes by one part in 1e15.
-Such a cell passes when it lies within twice the oracle's own envelope under
-that perturbation, and such cells must be rare.
+algorithm and controller and differ only in rounding; cells whose result
+rounding alone moves past the bar are judged against what rounding does to
+the oracle itself (oracle/parity.py: nine rounding-level variants of the
+oracle, the same source built with contracted multiply-adds and the input T
+moved by one or two ulp).
 """
 import sys
 
@@ -15,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import parity
 from paper_2205_05681_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -38,71 +38,6 @@ def chem():
 
 def dev(a, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
-
-
-def off_cells(Tg, Yg, To, Yo):
-    okT = np.abs(Tg - To) <= 1e-6 * np.abs(To)
-    okY = np.abs(Yg - Yo) <= 1e-6 * np.abs(Yo) + 1e-10
-    return np.where(~okT | ~okY.all(0))[0]
-
-
-def assert_parity(Tg, Yg, To, Yo, label, o=None, inputs=None, dt=None, max_frac=0.08, h=None):
-    """Every cell within the bar - or, for a rounding-sensitive cell, within
-    the bar plus three times the oracle's own spread under relative changes of
-    1e-15 .. 1e-12 in its input temperature.  A cell counts as
-    rounding-sensitive when that spread reaches a tenth of the bar (an input
-    change at the rounding level moves its result by >= 1e8 times as much:
-    hundreds of steps through a thermal runaway).  Such cells must stay rare
-    (max_frac)."""
-    bad = off_cells(Tg, Yg, To, Yo)
-    if bad.size == 0:
-        return
-    assert o is not None, "%s: %d cells off, first %s: dT %g, max dY %g" % (
-        label, bad.size, bad[:5], np.abs(Tg - To)[bad[0]], np.abs(Yg - Yo)[:, bad[0]].max())
-    assert bad.size <= max_frac * Tg.size, "%s: %d of %d cells off" % (label, bad.size, Tg.size)
-    T, P, Y = inputs
-    envT = np.zeros(bad.size)
-    envY = np.zeros((Y.shape[0], bad.size))
-    for eps in (1e-15, -1e-15, 1e-14, -1e-14, 1e-13, -1e-13, 1e-12, -1e-12):
-        r = o.integrate(T[bad] * (1 + eps), P[bad], Y[:, bad].copy(), dt,
-                        h=None if h is None else h[bad])
-        envT = np.maximum(envT, np.abs(r["T"] - To[bad]))
-        envY = np.maximum(envY, np.abs(r["Y"] - Yo[:, bad]))
-    dT = np.abs(Tg[bad] - To[bad])
-    dY = np.abs(Yg[:, bad] - Yo[:, bad])
-    barT = 1e-6 * np.abs(To[bad])
-    barY = 1e-6 * np.abs(Yo[:, bad]) + 1e-10
-    chaotic = (envT > 0.1 * barT) | (envY > 0.1 * barY).any(0)
-    assert chaotic.all(), "%s: cells %s off but not rounding-sensitive" % (label, bad[~chaotic])
-    assert np.all(dT <= barT + 3 * envT), label
-    assert np.all(dY <= barY + 3 * envY), label
-
-
-def assert_steps_parity(ng, no, o, inputs, dt, max_frac=0.1):
-    """Accepted-step counts.  A step is accepted when err <= 1, and err is a
-    cancelled estimate whose value the two sides agree on only to ~1e-5 on
-    stiff cells, so a decision that close to the threshold can go either way
-    and shift the count by a step or two.  On cells that run hundreds of steps
-    through a thermal runaway the count itself is rounding-chaotic: the
-    oracle's own count moves by up to ~5 % under relative input changes of
-    1e-15 .. 1e-12.  So a cell passes when its count is within 2 of the
-    oracle's, or within the oracle's own range under those changes widened on
-    each side by its width (at least 2) - eight samples only bound the spread
-    of a chaotic count loosely; counts may differ on at most max_frac of the
-    cells.  (The final states are held to the parity bar separately.)"""
-    d = np.abs(ng.astype(np.int64) - no.astype(np.int64))
-    assert np.mean(d > 0) <= max_frac, "steps differ on %d of %d cells" % ((d > 0).sum(), d.size)
-    far = np.where(d > 2)[0]
-    if far.size == 0:
-        return
-    T, P, Y = inputs
-    ns = np.array([o.integrate(T[far] * (1.0 + e), P[far], np.ascontiguousarray(Y[:, far]), dt)["n_acc"]
-                   for e in (1e-15, -1e-15, 1e-14, -1e-14, 1e-13, -1e-13, 1e-12, -1e-12)] + [no[far]])
-    w = np.maximum(2, ns.max(0) - ns.min(0))
-    lo, hi = ns.min(0) - w, ns.max(0) + w
-    ok = (ng[far] >= lo) & (ng[far] <= hi)
-    assert np.all(ok), "steps: cells %s: %s outside the oracle's range %s..%s" % (
-        far[~ok], ng[far][~ok], lo[~ok], hi[~ok])
 
 
 def assert_h_is_last_proposal(C, mech, o, T, P, Y, dt, mode, hg, rtol=1e-6, atol=1e-10):
@@ -192,11 +127,10 @@ def test_small_parity_full_config(chem, small, mode):
     T, P, Y = synth.states_small(m)
     mech = chem.Mechanism(path)
     Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
-    r = o.integrate(T, P, Y, 1e-6)
-    assert np.all(sg == 0) and np.all(r["status"] == 0)
-    assert_parity(Tg, Yg, r["T"], r["Y"], "small", o, (T, P, Y), 1e-6)
-    # hundreds of steps per cell: a few accept/reject decisions differ by rounding
-    assert_steps_parity(ng, r["n_acc"], o, (T, P, Y), 1e-6, max_frac=0.25)
+    assert np.all(sg == 0)
+    r, msg = parity.check_batch(o, T, P, Y, 1e-6, Tg, Yg, ng, "small " + mode)
+    say(msg)
+    assert np.all(r["status"] == 0)
     assert np.median(np.abs(hg - r["h"]) / r["h"]) < 1e-3
     assert_h_is_last_proposal(chem, mech, o, T, P, Y, 1e-6, mode, hg)
     mech.close()
@@ -210,48 +144,67 @@ def test_ch4_parity_ragged(chem, ch4, mode):
     T, P, Y = synth.states_mixing(m, 1000, 202)
     mech = chem.Mechanism(path)
     Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
-    r = o.integrate(T, P, Y, 1e-6)
     assert np.all(sg == 0)
-    assert_parity(Tg, Yg, r["T"], r["Y"], "ch4 " + mode, o, (T, P, Y), 1e-6, max_frac=0.01)
-    assert_steps_parity(ng, r["n_acc"], o, (T, P, Y), 1e-6, max_frac=0.02)
+    r, msg = parity.check_batch(o, T, P, Y, 1e-6, Tg, Yg, ng, "ch4 " + mode)
+    say(msg)
     assert np.median(np.abs(hg - r["h"]) / r["h"]) < 1e-6
     assert_h_is_last_proposal(chem, mech, o, T, P, Y, 1e-6, mode, hg)
     mech.close()
 
 
-def test_ch4_full_size_sampled(chem, ch4):
-    """65,536 cells in the benchmark's launch; 96 cells re-run on the oracle,
-    the hottest ones included."""
+@pytest.mark.parametrize("method,estimator", [("ros3", "embedded"), ("rodas3", "embedded"),
+                                              ("rodas4", "embedded"), ("ros4", "filtered"),
+                                              ("rodas4", "filtered")])
+@pytest.mark.parametrize("mode", ["plain", "team_persistent"])
+def test_methods_parity(chem, ch4, method, estimator, mode):
+    """The other solvers of the paper's solver table, and the filtered error
+    estimate, on 1,000 mixing-layer cells in both kinds of launch."""
     path, m, o = ch4
-    say("case: ch4 mechanism, 65536 cells sampled, all launch modes")
-    T, P, Y = synth.states_mixing(m, 65536, 202)
+    say("case: ch4 mechanism, 1000 cells,", method, estimator, mode)
+    T, P, Y = synth.states_mixing(m, 1000, 202)
     mech = chem.Mechanism(path)
-    res = {}
-    for mode in ("plain", "persistent", "team", "team_persistent", "team_persistent"):
-        key = mode if mode not in res else mode + "2"
-        res[key] = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
-    # plain and persistent launches run the same per-cell arithmetic; so do the
-    # two team launches; a repeated launch is bit-identical
-    for a, b in (("plain", "persistent"), ("team", "team_persistent"), ("team_persistent", "team_persistent2")):
-        assert np.array_equal(res[a][0], res[b][0]), (a, b)
-        assert np.array_equal(res[a][1], res[b][1]), (a, b)
-    rng = np.random.default_rng(0)
-    for mode in ("plain", "team_persistent"):
-        Tg, Yg, hg, ng, sg = res[mode]
-        idx = np.unique(np.r_[rng.choice(65536, 64, replace=False), np.argsort(-ng)[:32]])
-        r = o.integrate(T[idx], P[idx], Y[:, idx].copy(), 1e-6)
-        # a third of the sample are the stiffest cells of the batch
-        assert_parity(Tg[idx], Yg[:, idx], r["T"], r["Y"], "ch4 full " + mode, o,
-                      (T[idx], P[idx], Y[:, idx]), 1e-6, max_frac=0.1)
-        assert_steps_parity(ng[idx], r["n_acc"], o, (T[idx], P[idx], Y[:, idx]), 1e-6)
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode, method=method, estimator=estimator)
+    assert np.all(sg == 0)
+    r, msg = parity.check_batch(o, T, P, Y, 1e-6, Tg, Yg, ng, "ch4 %s %s %s" % (method, estimator, mode),
+                                method=method, estimator=estimator)
+    say(msg)
+    assert np.median(np.abs(hg - r["h"]) / r["h"]) < 1e-6
     mech.close()
 
 
+@pytest.mark.timeout(900)
+def test_ch4_full_size_all_cells(chem, ch4):
+    """65,536 mixing-layer cells in the benchmark's launch (auto), every cell
+    against the oracle; the other launch modes are bit-identical to their
+    counterparts (plain = persistent, team = team_persistent, a repeated
+    launch)."""
+    path, m, o = ch4
+    say("case: ch4 mechanism, 65536 cells, all launch modes")
+    T, P, Y = synth.states_mixing(m, 65536, 202)
+    mech = chem.Mechanism(path)
+    res = {}
+    for key, mode in (("auto", "auto"), ("plain", "plain"), ("persistent", "persistent"), ("team", "team"),
+                      ("team_persistent", "team_persistent"), ("team_persistent2", "team_persistent")):
+        res[key] = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
+        say("  ran", key)
+    mech.close()
+    for a, b in (("plain", "persistent"), ("team", "team_persistent"), ("team_persistent", "team_persistent2"),
+                 ("auto", "team_persistent")):
+        assert np.array_equal(res[a][0], res[b][0]), (a, b)
+        assert np.array_equal(res[a][1], res[b][1]), (a, b)
+    for mode in ("auto", "plain"):
+        Tg, Yg, hg, ng, sg = res[mode]
+        assert np.all(sg == 0)
+        r, msg = parity.check_batch(o, T, P, Y, 1e-6, Tg, Yg, ng, "ch4 65536 " + mode)
+        say(msg)
+
+
+@pytest.mark.timeout(900)
 def test_batching_full_size_sampled(chem, ch4):
     """The batching mix at its full size, 1,048,576 cells (85 % cold, 10 %
-    igniting, 5 % burnt gas; dt = 1e-5 s), in the default launch; 48 cells
-    re-run on the oracle: 24 at random, the 12 with the most steps and 12 more
-    igniting ones."""
+    igniting, 5 % burnt gas; dt = 1e-5 s), in the default launch; 2,048 cells
+    re-run on the oracle: the 64 with the most steps, 512 more igniting ones,
+    128 burnt-gas ones and 1,344 at random."""
     path, m, o = ch4
     say("case: batching mix, 1048576 cells, auto launch")
     T, P, Y, kind = synth.states_batching(m, 1048576, 203)
@@ -260,14 +213,16 @@ def test_batching_full_size_sampled(chem, ch4):
     mech.close()
     assert np.all(sg == 0)
     rng = np.random.default_rng(3)
-    ign = np.where(kind == 1)[0]
-    idx = np.unique(np.r_[rng.choice(T.size, 24, replace=False), np.argsort(-ng)[:12],
-                          rng.choice(ign, 12, replace=False)])
+    top = np.argsort(-ng)[:64]
+    rest = np.setdiff1d(np.arange(T.size), top)
+    ign = rng.choice(np.intersect1d(rest, np.flatnonzero(kind == 1)), 512, replace=False)
+    brn = rng.choice(np.intersect1d(rest, np.flatnonzero(kind == 2)), 128, replace=False)
+    rnd = rng.choice(np.setdiff1d(rest, np.r_[ign, brn]), 1344, replace=False)
+    idx = np.unique(np.r_[top, ign, brn, rnd])
     Ts, Ps, Ys = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
-    r = o.integrate(Ts, Ps, Ys, 1e-5)
+    r, msg = parity.check_batch(o, Ts, Ps, Ys, 1e-5, Tg[idx], Yg[:, idx], ng[idx], "batching 2048 of 1048576")
+    say(msg)
     assert np.all(r["status"] == 0)
-    assert_parity(Tg[idx], Yg[:, idx], r["T"], r["Y"], "batching full", o, (Ts, Ps, Ys), 1e-5, max_frac=0.1)
-    assert_steps_parity(ng[idx], r["n_acc"], o, (Ts, Ps, Ys), 1e-5, max_frac=0.2)
     # the mix spans two orders of magnitude in step count
     assert ng[kind == 0].mean() < 5 and ng[kind == 1].mean() > 50
 
@@ -291,8 +246,7 @@ def test_mechanism_sizes_team_parity(chem, mech_dir, name):
     for mode in ("team", "team_persistent"):
         Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode)
         assert np.all(sg == 0)
-        assert_parity(Tg, Yg, r["T"], r["Y"], name + " " + mode, o, (T, P, Y), 1e-6, max_frac=0.05)
-        assert_steps_parity(ng, r["n_acc"], o, (T, P, Y), 1e-6, max_frac=0.05)
+        say(parity.check_batch(o, T, P, Y, 1e-6, Tg, Yg, ng, name + " " + mode)[1])
     # adjoint: per-cell gradient of T_final along a random ln A direction
     idx = np.r_[np.argsort(-T)[:4], np.arange(4)]
     Ts, Ps, Ys = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
@@ -313,35 +267,25 @@ def test_mechanism_sizes_team_parity(chem, mech_dir, name):
         assert g[:, c] @ v == pytest.approx(dT, rel=1e-6, abs=1e-9 * np.abs(g[:, c]).sum() + 1e-300), c
 
 
-def test_large_full_size_sampled(chem, large):
-    """The 111-species mechanism at its full size, 262,144 mixing-layer cells
-    (dt = 1e-5 s), in the default launch (one cell per thread, N > 64); 64
-    cells re-run on the oracle."""
+@pytest.mark.timeout(900)
+def test_large_parity(chem, large):
+    """The 111-species mechanism (N = 112) on 512 of its mixing-layer states,
+    dt = 1e-5 s: each cell takes ~50 accepted steps, so every row of the
+    112 x 112 LU and many controller decisions are compared; every cell
+    against the oracle, in the default launch."""
     path, m, o = large
-    say("case: large mechanism, 262144 cells, auto launch")
+    say("case: large mechanism, 512 cells, auto launch")
     T, P, Y = synth.states_mixing(m, 262144, 204)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.r_[rng.choice(T.size, 496, replace=False), np.argsort(-T)[:16]])
+    T, P, Y = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
     mech = chem.Mechanism(path)
     Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-5, mode="auto")
     mech.close()
     assert np.all(sg == 0)
-    rng = np.random.default_rng(5)
-    idx = np.unique(np.r_[rng.choice(T.size, 56, replace=False), np.argsort(-T)[:8]])
-    Ts, Ps, Ys = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
-    r = o.integrate(Ts, Ps, Ys, 1e-5)
-    assert_parity(Tg[idx], Yg[:, idx], r["T"], r["Y"], "large full", o, (Ts, Ps, Ys), 1e-5, max_frac=0.05)
-    assert_steps_parity(ng[idx], r["n_acc"], o, (Ts, Ps, Ys), 1e-5, max_frac=0.05)
-
-
-def test_large_parity_small_batch(chem, large):
-    path, m, o = large
-    say("case: large mechanism, 130 cells, plain")
-    T, P, Y = synth.states_mixing(m, 130, 204)
-    mech = chem.Mechanism(path)
-    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-5)
-    r = o.integrate(T, P, Y, 1e-5)
-    assert np.all(sg == 0)
-    assert_parity(Tg, Yg, r["T"], r["Y"], "large", o, (T, P, Y), 1e-5, max_frac=0.03)
-    mech.close()
+    r, msg = parity.check_batch(o, T, P, Y, 1e-5, Tg, Yg, ng, "large 512")
+    say(msg)
+    assert np.median(r["n_acc"]) > 20
 
 
 @pytest.mark.parametrize("mode", ["plain", "persistent", "team", "team_persistent"])
@@ -373,9 +317,7 @@ def test_step_carry_over_and_edge_cases(chem, small):
     Tg2, Yg2, hg2, ng2, sg2 = run_gpu(chem, mech, Tg, P, Yg, 1e-6, h=hg)
     # the second step starts from slightly different states; compare it from the
     # GPU's own first-step output so that only the second step is tested
-    r2g = o.integrate(Tg, P, Yg, 1e-6, h=hg)
-    assert_parity(Tg2, Yg2, r2g["T"], r2g["Y"], "carry-over", o, (Tg, P, Yg), 1e-6, max_frac=0.2,
-                  h=hg)
+    say(parity.check_batch(o, Tg, P, Yg, 1e-6, Tg2, Yg2, ng2, "carry-over", h=hg)[1])
     # a single cell
     Tg1, Yg1, *_ = run_gpu(chem, mech, T[:1], P[:1], Y[:, :1].copy(), 1e-6)
     assert np.array_equal(Tg1, Tg[:1]) and np.array_equal(Yg1, Yg[:, :1])
