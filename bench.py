@@ -45,8 +45,8 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 KERNEL_SOURCES = ["paper_2205_05681_amd/csrc/integrate.hip", "paper_2205_05681_amd/csrc/team.h",
-                  "paper_2205_05681_amd/csrc/kinetics.h", "paper_2205_05681_amd/csrc/methods.h",
-                  "paper_2205_05681_amd/csrc/mech.h"]
+                  "paper_2205_05681_amd/csrc/team4.h", "paper_2205_05681_amd/csrc/kinetics.h",
+                  "paper_2205_05681_amd/csrc/methods.h", "paper_2205_05681_amd/csrc/mech.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_team_kernel_batching_1048576.json")
 METRIC = "cells/s per split step at rtol 1e-6 (plain vs persistent); adjoint/forward cost"
 
@@ -235,8 +235,9 @@ def large(c, a):
     att, acc, rej, ns, st = run_stats(c, mech, m, Tt, Pt, Yt, 1e-5)
     flops, _ = c.opcount.batch_flops(m, att, acc)
     mech.close()
-    return {"workload": "111-species mechanism (784 reactions: 60 third-body, 40 Troe), the first %d of the "
-                        "262,144 mixing-layer cells, dt=1e-5 s" % n,
+    return {"workload": "111-species mechanism (784 reactions: 60 third-body, 40 Troe), %s of the "
+                        "262,144 mixing-layer cells, dt=1e-5 s, default launch (four wavefronts per cell)"
+                        % ("all" if n == 262144 else "the first %d" % n),
             "cells": n, "cells_per_s": round(n / t, 1), "ms_per_call": round(t * 1e3, 3),
             "attempted_steps": att, "accepted_steps": acc, "failed_cells": int((st != 0).sum()),
             "fp64_tflops": round(flops / t / 1e12, 4), "frac": round(flops / t / 1e12 / FP64_PEAK_TFLOPS, 6)}
@@ -298,6 +299,53 @@ def adjoint_cost(c, a):
             "gradient_over_forward": round((t_ck + t_adj) / t_fwd, 3)}
 
 
+def work_precision(c, a):
+    """The paper's verification study (Sec. 3.1) on synthetic states: each
+    solver at tolerances 1e-4 .. 1e-12 (rtol = atol), error against a tight
+    reference in the norm of eqs. (ivp_norm)/(error_norm) - per cell the
+    2-norm over (T, Y) of |y_ref - y| / (1e-10 + 1e-6 |y_ref|), then the
+    largest over cells - and GPU time per call.  States: a sample of the
+    65,536 mixing-layer cells (the 64 with the most steps and the rest at
+    random), dt = 1e-6 s.  Reference: the CPU oracle with RODAS4 at
+    rtol = 1e-14, atol = 1e-20 (the paper uses CVODES at 1e-15 / 1e-20)."""
+    import oracle
+    np, chem, synth = c.np, c.chem, c.synth
+    path, m = synth.mechanism_file("ch4", c.mech_dir)
+    T, P, Y = synth.states_mixing(m, 65536, 202)
+    mech = chem.Mechanism(path, device=0)
+    Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
+    ns = chem.integrate(mech, Tt, Pt, Yt, 1e-6)[3].cpu().numpy()
+    top = np.argsort(-ns)[:64]
+    rng = np.random.default_rng(11)
+    idx = np.unique(np.r_[top, rng.choice(np.setdiff1d(np.arange(T.size), top), a.wp_cells - 64, replace=False)])
+    T, P, Y = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+    log("work-precision: reference on %d cells" % idx.size)
+    t0 = time.time()
+    ref = oracle.Oracle(path).integrate(T, P, Y, 1e-6, rtol=1e-14, atol=1e-20, method="rodas4")
+    t_ref = time.time() - t0
+    yref = np.vstack([ref["T"], ref["Y"]])
+    Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
+    pts = []
+    for meth in ("ros3", "ros4", "rodas3", "rodas4"):
+        for est in ("embedded", "filtered"):
+            for e in range(4, 13):
+                tol = 10.0 ** -e
+                o = chem.default_opts(method=meth, estimator=est)
+                r = chem.integrate(mech, Tt, Pt, Yt, 1e-6, rtol=tol, atol=tol, opts=o)
+                t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, rtol=tol, atol=tol, opts=o))
+                y = np.vstack([r[0].cpu().numpy(), r[1].cpu().numpy()])
+                E = np.sqrt((((yref - y) / (1e-10 + 1e-6 * np.abs(yref))) ** 2).sum(0))
+                pts.append({"method": meth, "estimator": est, "tol": tol, "error_norm": float(E.max()),
+                            "error_norm_median": float(np.median(E)), "ms": round(t * 1e3, 3),
+                            "failed": int((r[4] != 0).sum().item())})
+            log("work-precision: %s %s done" % (meth, est))
+    mech.close()
+    return {"workload": "%d of the 65,536 CH4 mixing-layer cells (64 with the most steps), dt=1e-6 s" % idx.size,
+            "reference": "oracle RODAS4, rtol 1e-14, atol 1e-20, %.1f s on %d threads" % (t_ref, ref["threads"]),
+            "norm": "max over cells of the 2-norm over (T, Y) of |y_ref - y| / (1e-10 + 1e-6 |y_ref|)",
+            "points": pts}
+
+
 def oracle_rate(oracle, path, T, P, Y, dt, budget_s, threads=0, chunk=256):
     """The oracle (as it is) on the given cells in order, in chunks, until about
     budget_s seconds of wall time; returns (cells/s, cells done, seconds, threads)."""
@@ -357,12 +405,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cells", type=int, default=1048576, help="headline batch size")
-    ap.add_argument("--large-cells", type=int, default=4096)
+    ap.add_argument("--large-cells", type=int, default=262144)
     ap.add_argument("--adjoint-cells", type=int, default=16384)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--skip", default="", help="comma list of legs to skip: mixing,methods,large,small,adjoint")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 256 MiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--work-precision", default="",
+                    help="run only the work-precision sweep and write its JSON to this file")
+    ap.add_argument("--wp-cells", type=int, default=2048)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported "
@@ -377,6 +430,18 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     c = Ctx(torch, np, chem, synth, opcount, dev, tempfile.mkdtemp(prefix="chem_bench_"))
+    if a.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        c.sync()
+        del src, dst
+    if a.work_precision:
+        wp = work_precision(c, a)
+        with open(a.work_precision, "w") as f:
+            json.dump(wp, f)
+        print(json.dumps({"work_precision": a.work_precision, "points": len(wp["points"])}), flush=True)
+        return
     head, head_data = headline(c, a)
     skip = set(a.skip.split(",")) if a.skip else set()
     if a.quick:

@@ -61,8 +61,10 @@ extern "C" {
 #define CHEM_MODE_AUTO 0        /* autotuned choice (cached per mechanism/size) */
 #define CHEM_MODE_PLAIN 1       /* one cell per thread, one launch of ceil(n/wg) groups */
 #define CHEM_MODE_PERSISTENT 2  /* one cell per thread, resident grid, atomic work queue */
-#define CHEM_MODE_TEAM 3        /* one wavefront per cell (J and LU in registers/LDS) */
-#define CHEM_MODE_TEAM_PERSISTENT 4 /* one wavefront per cell, resident grid, work queue */
+#define CHEM_MODE_TEAM 3        /* a team per cell: one wavefront (N <= 64) or a work-group of
+                                   four (N <= 128); J and LU in LDS and registers */
+#define CHEM_MODE_TEAM_PERSISTENT 4 /* a team per cell, resident grid, work queue.  Above
+                                   N = 128 both team modes run one cell per thread. */
 
 /* ---- dispatch order (chem_opts.order) ---------------------------------- */
 #define CHEM_ORDER_INDEX 0      /* cells are taken in index order */
@@ -107,9 +109,9 @@ typedef struct {
   int32_t order;          /* dispatch order of the cells: CHEM_ORDER_* (CHEM_ORDER_HOT_FIRST) */
   int32_t method;         /* CHEM_METHOD_* (CHEM_METHOD_ROS4) */
   int32_t estimator;      /* CHEM_EST_* (CHEM_EST_EMBEDDED) */
-  int32_t team_waves;     /* team modes: wavefronts per cell; 0 = library choice (one per cell
-                             for N <= 64, which is the only size built: other values are
-                             CHEM_EINVAL) */
+  int32_t team_waves;     /* team modes: wavefronts per cell, 0 = library choice: 1 for
+                             N <= 64, 4 for 64 < N <= 128 (the only sizes each is built for:
+                             another value is CHEM_EUNSUPPORTED; not 0, 1 or 4: CHEM_EINVAL) */
   unsigned long long* stats; /* nullable DEVICE pointer to 3 counters that the call adds to:
                                 attempted steps, accepted steps, rejected steps (all cells) */
 } chem_opts;
@@ -200,9 +202,11 @@ int64_t chem_ckpt_records(chem_ckpt_t c);
 int chem_ckpt_export(chem_ckpt_t c, int64_t* off, double* records);
 
 /* Autotuner.  Times the launch configurations (one wavefront per cell,
- * plain or persistent with 1..4 resident waves per CU; and, for mechanisms
- * with N <= 16, one cell per thread with 64- or 256-thread groups) on a
- * stratified sample of up to 4096 cells of the given batch, two runs each,
+ * plain or persistent with 1..4 resident waves per CU, or a work-group of four
+ * wavefronts per cell for 64 < N <= 128; and, for mechanisms with N <= 16 or
+ * N > 128, one cell per thread with 64- or 256-thread groups) on a strided
+ * sample of the given batch - sixteen cells per resident wavefront of the
+ * device (16,384 on MI355X), at least 4,096 - two runs each,
  * and keeps the fastest for this mechanism and the batch-size bucket
  * floor(log2(n_cells)).  CHEM_MODE_AUTO then uses it.  The choice is kept
  * with the handle and, when the environment variable CHEM_AUTOTUNE_CACHE

@@ -33,6 +33,7 @@
 #include "mech.h"
 #include "methods.h"
 #include "team.h"
+#include "team4.h"
 #include "adjoint.h"
 
 namespace chem {
@@ -503,6 +504,201 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       unsigned c1 = 0;
       if (lane == 0) c1 = atomicAdd(p.queue, 1u);
       q = (unsigned)__shfl((int)c1, 0, 64);
+    } else {
+      break;
+    }
+  }
+}
+
+
+// ------------------------------------------------------------------ four wavefronts per cell (64 < N <= 128)
+// The same integrator as integrate_team_kernel, on a work-group of four
+// wavefronts per cell (team4.h).  Every wavefront holds the state and stage
+// vectors and runs the same controller, so all its decisions are uniform over
+// the work-group; source terms, Jacobian and LU are split over the 256 threads.
+__global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool PERSISTENT) {
+  extern __shared__ double lds_raw[];
+  const MechView& M = p.M;
+  const int N = M.N, K = M.K, ldj = N + 1;
+  const int tid = t4_tid(), w = t4_wave(), lane = t4_lane();
+  Team4Lds L;
+  L.bind(lds_raw, N);
+  double* const ust = L.ust + w * (MAX_STAGES * 128);   // this wavefront's stage vectors
+  double* const jsv = p.jsave ? p.jsave + (int64_t)blockIdx.x * N * N : nullptr;
+  int64_t q;
+  if (PERSISTENT) {
+    if (tid == 0) L.misc[0] = (int)atomicAdd(p.queue, 1u);
+    wsync();
+    q = (unsigned)L.misc[0];
+    wsync();
+  } else {
+    q = blockIdx.x;
+  }
+  while (q < p.n) {
+    const int64_t cell = p.order ? p.order[q] : q;
+    // ---- input conversion (eq. (conc_form1)), every wavefront
+    const double P = p.P[cell];
+    const double T0 = p.T_in[cell];
+    const double y0 = (lane < K) ? p.Y_in[(int64_t)lane * p.ldY + cell] / M.W[lane] : 0.0;
+    const double y1 = (64 + lane < K) ? p.Y_in[(int64_t)(64 + lane) * p.ldY + cell] / M.W[64 + lane] : 0.0;
+    const V2 yw{y0, y1};
+    const double inv = v2_sum(yw);
+    V2 phi;
+    {
+      const double s0 = v2_gather(yw, (lane + 126) & 127);   // element lane - 2 (lanes >= 2)
+      const double s1 = v2_gather(yw, 62 + lane);             // element 62 + lane
+      phi.a = (lane == 0) ? T0 : (lane == 1) ? RU * T0 * inv / P : s0;
+      phi.b = (64 + lane < N) ? s1 : 0.0;
+    }
+    double rem = p.dt, h = p.dt;
+    if (p.h_io && p.h_io[cell] > 0.0) h = p.h_io[cell];
+    int attempts = 0, accepted = 0, bad = 0, status = 0;
+    bool last_rej = false, need_jac = true;
+    bool done = (p.T_cut > 0.0) && !(T0 >= p.T_cut);
+    const int64_t ck_rec = p.ck_off ? p.ck_off[cell] : 0;
+    V2 f1{0.0, 0.0};
+    while (!done) {
+      if (attempts >= p.max_steps) {
+        status = CHEM_CELL_MAX_STEPS;
+        break;
+      }
+      if (h < p.h_min) {
+        status = CHEM_CELL_H_MIN;
+        break;
+      }
+      ++attempts;
+      const double hs = fmin(h, rem);
+      if (need_jac || !jsv) {
+        f1 = t4_rhs_jac(M, P, phi, L, p.lnA);
+        need_jac = false;
+        if (jsv && tid < N)
+          for (int i = 0; i < N; ++i) jsv[i * N + tid] = L.J[i * ldj + tid];
+      } else {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");   // own stores done, L1 invalidated
+        if (tid < N)
+          for (int i = 0; i < N; ++i) L.J[i * ldj + tid] = jsv[i * N + tid];
+        wsync();
+      }
+      const RosTable& R = p.tab;
+      const int rc = t4_lu(L.J, ldj, N, 1.0 / (hs * R.gamma), L);
+      double err = 0.0;
+      V2 ynew{0.0, 0.0};
+      if (rc == 0) {
+        const double* F = L.J;
+        V2 fs = f1;
+#pragma unroll 1
+        for (int i = 0; i < R.s; ++i) {
+          if (i > 0 && R.newf[i]) {
+            V2 y = phi;
+            for (int j = 0; j < i; ++j) {
+              y.a += R.a[i][j] * ust[128 * j + lane];
+              y.b += R.a[i][j] * ust[128 * j + 64 + lane];
+            }
+            fs = t4_rhs(M, P, y, L, p.lnA);
+          }
+          V2 r = fs;
+          for (int j = 0; j < i; ++j) {
+            r.a += (R.c[i][j] / hs) * ust[128 * j + lane];
+            r.b += (R.c[i][j] / hs) * ust[128 * j + 64 + lane];
+          }
+          const V2 u = t4_solve(F, ldj, N, L, r);
+          ust[128 * i + lane] = u.a;
+          ust[128 * i + 64 + lane] = u.b;
+        }
+        V2 e{0.0, 0.0};
+        ynew = phi;
+        for (int j = 0; j < R.s; ++j) {
+          const double ua = ust[128 * j + lane], ub = ust[128 * j + 64 + lane];
+          ynew.a += R.m[j] * ua;
+          ynew.b += R.m[j] * ub;
+          e.a += R.e[j] * ua;
+          e.b += R.e[j] * ub;
+        }
+        if (p.estimator == CHEM_EST_FILTERED) {
+          const V2 ef = t4_solve(F, ldj, N, L, e);
+          e.a = ef.a / (hs * R.gamma);
+          e.b = ef.b / (hs * R.gamma);
+        }
+        const double sa = p.atol + p.rtol * fmax(fabs(phi.a), fabs(ynew.a));
+        const double sb = p.atol + p.rtol * fmax(fabs(phi.b), fabs(ynew.b));
+        const double ra = (lane < N) ? e.a / sa : 0.0;
+        const double rb = (64 + lane < N) ? e.b / sb : 0.0;
+        err = sqrt(wave_sum(ra * ra + rb * rb) / N);
+      }
+      if (rc != 0 || !isfinite(err)) {
+        if (++bad >= 10) {
+          status = (rc == 1) ? CHEM_CELL_SINGULAR : CHEM_CELL_NONFINITE;
+          break;
+        }
+        h = hs * p.fac_min;
+        last_rej = true;
+        continue;
+      }
+      bad = 0;
+      double fac = (err > 0.0) ? p.safety * pow(err, -1.0 / p.tab.elo) : p.fac_max;
+      if (err <= 1.0) {
+        if (p.ck_data && ck_rec + accepted < p.ck_off[cell + 1] - 1 && w == 0) {
+          double* rec = p.ck_data + (ck_rec + accepted) * (int64_t)(N + 1);
+          rec[lane] = phi.a;
+          if (64 + lane < N) rec[64 + lane] = phi.b;
+          if (lane == 0) rec[N] = hs;
+        }
+        phi = ynew;
+        need_jac = true;
+        rem -= hs;
+        ++accepted;
+        fac = fmin(p.fac_max, fmax(p.fac_min, fac));
+        if (last_rej) fac = fmin(fac, 1.0);
+        last_rej = false;
+        h = hs * fac;
+        if (rem <= 0.0) break;
+      } else {
+        fac = fmin(1.0, fmax(p.fac_min, fac));
+        last_rej = true;
+        h = hs * fac;
+      }
+    }
+    if (w == 0) {
+      if (p.ck_data) {
+        double* rec = p.ck_data + (p.ck_off[cell + 1] - 1) * (int64_t)(N + 1);
+        rec[lane] = phi.a;
+        if (64 + lane < N) rec[64 + lane] = phi.b;
+        if (lane == 0) rec[N] = 0.0;
+      }
+      // ---- output conversion: n_K from the ideal-gas closure, Y_k = n_k W_k / mass
+      const double T = v2_get(phi, 0), V = v2_get(phi, 1);
+      const double n0 = v2_gather(phi, lane + 2);          // species lane
+      const double n1 = v2_gather(phi, (66 + lane) & 127); // species 64 + lane
+      const double h0 = (lane < K - 1) ? n0 : 0.0;
+      const double h1 = (64 + lane < K - 1) ? n1 : 0.0;
+      const double s = wave_sum(h0 + h1);
+      const double nb = P * V / (RU * T) - s;
+      const double nn0 = (lane < K - 1) ? h0 : (lane == K - 1 ? nb : 0.0);
+      const double nn1 = (64 + lane < K - 1) ? h1 : (64 + lane == K - 1 ? nb : 0.0);
+      const double m0 = (lane < K) ? nn0 * M.W[lane] : 0.0;
+      const double m1 = (64 + lane < K) ? nn1 * M.W[64 + lane] : 0.0;
+      const double mass = wave_sum(m0 + m1);
+      if (lane < K) p.Y_out[(int64_t)lane * p.ldY + cell] = m0 / mass;
+      if (64 + lane < K) p.Y_out[(int64_t)(64 + lane) * p.ldY + cell] = m1 / mass;
+      if (lane == 0) {
+        p.T_out[cell] = T;
+        if (p.h_io) p.h_io[cell] = h;
+        if (p.n_steps) p.n_steps[cell] = accepted;
+        if (p.status) p.status[cell] = status;
+        if (p.ck_count) p.ck_count[cell] = accepted;
+        if (p.stats) {
+          atomicAdd(&p.stats[0], (unsigned long long)attempts);
+          atomicAdd(&p.stats[1], (unsigned long long)accepted);
+          atomicAdd(&p.stats[2], (unsigned long long)(attempts - accepted));
+        }
+      }
+    }
+    if (PERSISTENT) {
+      wsync();   // every wavefront is done with this cell's LDS
+      if (tid == 0) L.misc[0] = (int)atomicAdd(p.queue, 1u);
+      wsync();
+      q = (unsigned)L.misc[0];
+      wsync();
     } else {
       break;
     }
@@ -1198,133 +1394,43 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
 
 // Dispatch order of the cells (hottest first) into w->order; *order receives
 // it, or null when the cells go in index order.  Four small kernels, no memset.
+// The four ordering kernels: bins[0..2*ORDER_BINS) are counts and cursors,
+// order[n] receives the queue position -> cell map.
+static int launch_order(int64_t n, const double* T_in, unsigned int* bins, int32_t* order,
+                        hipStream_t stream) {
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(order_clear_kernel, dim3(1), dim3(ORDER_BINS), 0, stream, bins);
+  hipLaunchKernelGGL(order_count_kernel, dim3(blocks), dim3(256), 0, stream, n, T_in, bins);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(ORDER_BINS), 0, stream, bins);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, n, T_in, bins, order);
+  HIPCHECK(hipGetLastError());
+  return CHEM_OK;
+}
+
+static bool wants_order(int32_t mode, int64_t n) { return mode == CHEM_ORDER_HOT_FIRST && n >= 1024; }
+
 static int build_order(chem_mech_t m, Workspace* w, int64_t n, const double* T_in, int32_t mode,
                        hipStream_t stream, const int32_t** order) {
   *order = nullptr;
-  if (mode != CHEM_ORDER_HOT_FIRST || n < 1024) return CHEM_OK;
+  if (!wants_order(mode, n)) return CHEM_OK;
   {
     std::lock_guard<std::mutex> g(m->mu);
     const int rc = grow((void**)&w->order, &w->order_bytes, (size_t)n * sizeof(int32_t));
     if (rc) return rc;
   }
-  unsigned int* bins = w->queue + 64;
-  const unsigned blocks = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(order_clear_kernel, dim3(1), dim3(ORDER_BINS), 0, stream, bins);
-  hipLaunchKernelGGL(order_count_kernel, dim3(blocks), dim3(256), 0, stream, n, T_in, bins);
-  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(ORDER_BINS), 0, stream, bins);
-  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, n, T_in, bins, w->order);
-  HIPCHECK(hipGetLastError());
+  const int rc = launch_order(n, T_in, w->queue + 64, w->order, stream);
+  if (rc) return rc;
   *order = w->order;
   return CHEM_OK;
 }
 
-static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const double* P,
-                          const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
-                          double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
-                          const double* lnA, const chem_opts* opts, double* ck_data,
-                          const int64_t* ck_off, int32_t* ck_count, hipStream_t stream) {
-
-  if (!m || n < 0 || n > INT32_MAX) return CHEM_EINVAL;
-  if (n > 0 && (!T_in || !P || !Y_in || !T_out || !Y_out)) return CHEM_EINVAL;
-  if (!(dt > 0) || !(rtol > 0) || !(atol >= 0) || ldY < n) return CHEM_EINVAL;
-  chem_opts o;
-  resolve_opts(m, n, opts, &o);
-  if (o.mode < CHEM_MODE_AUTO || o.mode > CHEM_MODE_TEAM_PERSISTENT) return CHEM_EINVAL;
-  if (o.wg_size < 0 || o.wg_size > 256 || (o.wg_size % 64) != 0) return CHEM_EINVAL;
-  if (o.max_steps <= 0 || !(o.fac_min > 0) || !(o.fac_max >= 1) || !(o.safety > 0)) return CHEM_EINVAL;
-  if (o.order != CHEM_ORDER_INDEX && o.order != CHEM_ORDER_HOT_FIRST) return CHEM_EINVAL;
-  if (o.method < 0 || o.method >= N_METHODS) return CHEM_EINVAL;
-  if (o.estimator != CHEM_EST_EMBEDDED && o.estimator != CHEM_EST_FILTERED) return CHEM_EINVAL;
-  if (o.team_waves != 0 && o.team_waves != 1) return CHEM_EINVAL;
-  if (n == 0) return CHEM_OK;
-  HIPCHECK(hipSetDevice(m->device));
-  int mode = o.mode;
-  if (mode == CHEM_MODE_AUTO) mode = (m->view.N <= 64) ? CHEM_MODE_TEAM_PERSISTENT : CHEM_MODE_PERSISTENT;
-  // one wavefront per cell needs N <= 64; larger mechanisms use one cell per thread
-  if (m->view.N > 64 && mode == CHEM_MODE_TEAM) mode = CHEM_MODE_PLAIN;
-  if (m->view.N > 64 && mode == CHEM_MODE_TEAM_PERSISTENT) mode = CHEM_MODE_PERSISTENT;
-  const bool persistent = (mode == CHEM_MODE_PERSISTENT || mode == CHEM_MODE_TEAM_PERSISTENT);
-  const bool team = (mode == CHEM_MODE_TEAM || mode == CHEM_MODE_TEAM_PERSISTENT);
-  if (team) {
-    Workspace* w;
-    int rc = get_workspace(m, stream, 0, &w);
-    if (rc) return rc;
-    const int32_t* order;
-    rc = build_order(m, w, n, T_in, o.order, stream, &order);
-    if (rc) return rc;
-    IntParams p;
-    memset(&p, 0, sizeof(p));
-    p.order = order;
-    p.M = m->view;
-    p.n = n;
-    p.T_in = T_in;
-    p.P = P;
-    p.Y_in = Y_in;
-    p.ldY = ldY;
-    p.T_out = T_out;
-    p.Y_out = Y_out;
-    p.dt = dt;
-    p.rtol = rtol;
-    p.atol = atol;
-    p.h_min = o.h_min;
-    p.safety = o.safety;
-    p.fac_min = o.fac_min;
-    p.fac_max = o.fac_max;
-    p.T_cut = o.T_cut;
-    p.max_steps = o.max_steps;
-    p.estimator = o.estimator;
-    p.tab = TABLES[o.method];
-    p.h_io = h_io;
-    p.n_steps = n_steps;
-    p.status = status;
-    p.lnA = lnA;
-    p.queue = w->queue;
-    p.stats = o.stats;
-    p.ck_data = ck_data;
-    p.ck_off = ck_off;
-    p.ck_count = ck_count;
-    TeamKernel kern = team_kernel(m->view.N);
-    const size_t lds = TeamLds::doubles(m->view.N) * sizeof(double);
-    unsigned grid = (unsigned)n;
-    if (persistent) {
-      int per_cu = 0;
-      HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds));
-      if (o.waves_per_cu > 0) per_cu = std::min(per_cu, o.waves_per_cu);
-      if (per_cu < 1) per_cu = 1;
-      grid = (unsigned)std::min<int64_t>((int64_t)m->n_cu * per_cu, n);
-      {
-        std::lock_guard<std::mutex> g(m->mu);
-        rc = grow((void**)&w->jsave, &w->jsave_bytes, (size_t)grid * m->view.N * m->view.N * sizeof(double));
-        if (rc) return rc;
-      }
-      p.jsave = w->jsave;
-      hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, w->queue);
-    }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, stream, p, persistent);
-    HIPCHECK(hipGetLastError());
-    return CHEM_OK;
-  }
-  const int wg = o.wg_size ? o.wg_size : 64;
-  int64_t slots;
-  if (persistent) {
-    int per_cu = 0;
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_thread_kernel<true>, wg, 0));
-    if (o.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, o.waves_per_cu * 64 / wg));
-    if (per_cu < 1) per_cu = 1;
-    slots = (int64_t)m->n_cu * per_cu * wg;
-    slots = std::min(slots, round_up(n, wg));
-  } else {
-    slots = round_up(n, wg);
-  }
-  Workspace* w;
-  int rc = get_workspace(m, stream, slots, &w);
-  if (rc) return rc;
-  const int32_t* order;
-  rc = build_order(m, w, n, T_in, o.order, stream, &order);
-  if (rc) return rc;
+// Parameters common to every launch.
+static IntParams make_params(chem_mech_t m, const chem_opts& o, int64_t n, const double* T_in,
+                             const double* P, const double* Y_in, int64_t ldY, double* T_out,
+                             double* Y_out, double dt, double rtol, double atol, double* h_io,
+                             int32_t* n_steps, int32_t* status, const double* lnA) {
   IntParams p;
   memset(&p, 0, sizeof(p));
-  p.order = order;
   p.M = m->view;
   p.n = n;
   p.T_in = T_in;
@@ -1348,6 +1454,113 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
   p.n_steps = n_steps;
   p.status = status;
   p.lnA = lnA;
+  p.stats = o.stats;
+  return p;
+}
+
+// One-wavefront-per-cell launch.  persistent: resident grid over the work
+// queue at `queue` (reset here by a kernel); jsave (nullable): per-work-group
+// J copies of the persistent grid, sized by jsave_grow (null: a rejected step
+// re-evaluates J at the same state, which gives the same J).
+static int team_launch(chem_mech_t m, const chem_opts& o, IntParams p, bool persistent,
+                       unsigned int* queue, Workspace* jsave_ws, hipStream_t stream) {
+  const int N = m->view.N;
+  const bool four = N > 64;             // four wavefronts per cell (N <= 128)
+  TeamKernel kern = four ? integrate_team4_kernel : team_kernel(N);
+  if (!kern) return CHEM_EUNSUPPORTED;
+  const int threads = four ? T4_THREADS : 64;
+  const size_t lds = (four ? Team4Lds::doubles(N) : TeamLds::doubles(N)) * sizeof(double);
+  if (lds > 65536)   // above the default dynamic-LDS limit of a launch
+    HIPCHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  unsigned grid = (unsigned)p.n;
+  p.queue = queue;
+  if (persistent) {
+    int per_cu = 0;
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds));
+    if (o.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, o.waves_per_cu * 64 / threads));
+    if (per_cu < 1) per_cu = 1;
+    grid = (unsigned)std::min<int64_t>((int64_t)m->n_cu * per_cu, p.n);
+    if (jsave_ws) {
+      std::lock_guard<std::mutex> g(m->mu);
+      const int rc = grow((void**)&jsave_ws->jsave, &jsave_ws->jsave_bytes,
+                          (size_t)grid * N * N * sizeof(double));
+      if (rc) return rc;
+      p.jsave = jsave_ws->jsave;
+    }
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, queue);
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, stream, p, persistent);
+  HIPCHECK(hipGetLastError());
+  return CHEM_OK;
+}
+
+static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const double* P,
+                          const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
+                          double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
+                          const double* lnA, const chem_opts* opts, double* ck_data,
+                          const int64_t* ck_off, int32_t* ck_count, hipStream_t stream) {
+
+  if (!m || n < 0 || n > INT32_MAX) return CHEM_EINVAL;
+  if (n > 0 && (!T_in || !P || !Y_in || !T_out || !Y_out)) return CHEM_EINVAL;
+  if (!(dt > 0) || !(rtol > 0) || !(atol >= 0) || ldY < n) return CHEM_EINVAL;
+  chem_opts o;
+  resolve_opts(m, n, opts, &o);
+  if (o.mode < CHEM_MODE_AUTO || o.mode > CHEM_MODE_TEAM_PERSISTENT) return CHEM_EINVAL;
+  if (o.wg_size < 0 || o.wg_size > 256 || (o.wg_size % 64) != 0) return CHEM_EINVAL;
+  if (o.max_steps <= 0 || !(o.fac_min > 0) || !(o.fac_max >= 1) || !(o.safety > 0)) return CHEM_EINVAL;
+  if (o.order != CHEM_ORDER_INDEX && o.order != CHEM_ORDER_HOT_FIRST) return CHEM_EINVAL;
+  if (o.method < 0 || o.method >= N_METHODS) return CHEM_EINVAL;
+  if (o.estimator != CHEM_EST_EMBEDDED && o.estimator != CHEM_EST_FILTERED) return CHEM_EINVAL;
+  if (o.team_waves != 0 && o.team_waves != 1 && o.team_waves != 4) return CHEM_EINVAL;
+  if (n == 0) return CHEM_OK;
+  HIPCHECK(hipSetDevice(m->device));
+  int mode = o.mode;
+  // one or four wavefronts per cell need N <= 128; larger mechanisms use one cell per thread
+  const bool team_ok = m->view.N <= T4_NMAX;
+  if (o.team_waves != 0 && !team_ok) return CHEM_EUNSUPPORTED;
+  if (o.team_waves == 1 && m->view.N > 64) return CHEM_EUNSUPPORTED;
+  if (o.team_waves == 4 && m->view.N <= 64) return CHEM_EUNSUPPORTED;
+  if (mode == CHEM_MODE_AUTO) mode = team_ok ? CHEM_MODE_TEAM_PERSISTENT : CHEM_MODE_PERSISTENT;
+  if (!team_ok && mode == CHEM_MODE_TEAM) mode = CHEM_MODE_PLAIN;
+  if (!team_ok && mode == CHEM_MODE_TEAM_PERSISTENT) mode = CHEM_MODE_PERSISTENT;
+  const bool persistent = (mode == CHEM_MODE_PERSISTENT || mode == CHEM_MODE_TEAM_PERSISTENT);
+  const bool team = (mode == CHEM_MODE_TEAM || mode == CHEM_MODE_TEAM_PERSISTENT);
+  if (team) {
+    Workspace* w;
+    int rc = get_workspace(m, stream, 0, &w);
+    if (rc) return rc;
+    const int32_t* order;
+    rc = build_order(m, w, n, T_in, o.order, stream, &order);
+    if (rc) return rc;
+    IntParams p = make_params(m, o, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
+                              status, lnA);
+    p.order = order;
+    p.ck_data = ck_data;
+    p.ck_off = ck_off;
+    p.ck_count = ck_count;
+    return team_launch(m, o, p, persistent, w->queue, w, stream);
+  }
+  const int wg = o.wg_size ? o.wg_size : 64;
+  int64_t slots;
+  if (persistent) {
+    int per_cu = 0;
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, integrate_thread_kernel<true>, wg, 0));
+    if (o.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, o.waves_per_cu * 64 / wg));
+    if (per_cu < 1) per_cu = 1;
+    slots = (int64_t)m->n_cu * per_cu * wg;
+    slots = std::min(slots, round_up(n, wg));
+  } else {
+    slots = round_up(n, wg);
+  }
+  Workspace* w;
+  int rc = get_workspace(m, stream, slots, &w);
+  if (rc) return rc;
+  const int32_t* order;
+  rc = build_order(m, w, n, T_in, o.order, stream, &order);
+  if (rc) return rc;
+  IntParams p = make_params(m, o, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
+                            status, lnA);
+  p.order = order;
   p.ws = w->ws;
   p.piv = w->piv;
   p.ld = slots;
@@ -1439,7 +1652,13 @@ int chem_autotune(chem_mech_t m, int64_t n, const double* T_in, const double* P,
   if (!m || n <= 0 || !T_in || !P || !Y_in || ldY < n) return CHEM_EINVAL;
   HIPCHECK(hipSetDevice(m->device));
   const int K = m->view.K, N = m->view.N;
-  const int64_t ns = std::min<int64_t>(n, 4096);
+  // The sample must load the device the way the batch will: with a few cells
+  // per resident slot, every candidate waits on the sample's slowest cell and
+  // the timings cannot tell the occupancies apart (measured: a 4,096-cell
+  // sample of the batching mix picked 2 waves per CU, half the throughput of
+  // 4 on the full batch).  Sixteen cells per resident wavefront at the
+  // largest occupancy tried, at least 4,096.
+  const int64_t ns = std::min<int64_t>(n, std::max<int64_t>(4096, 16 * 4 * (int64_t)m->n_cu));
   const int64_t stride = n / ns;
   double *Ts = nullptr, *Ps = nullptr, *Ys = nullptr, *To = nullptr, *Yo = nullptr;
   auto cleanup = [&]() {
@@ -1465,8 +1684,12 @@ int chem_autotune(chem_mech_t m, int64_t n, const double* T_in, const double* P,
   if (N <= 64) {
     add(CHEM_MODE_TEAM, 0, 0);
     for (int w : {0, 2, 3, 4}) add(CHEM_MODE_TEAM_PERSISTENT, 0, w);
+  } else if (N <= T4_NMAX) {
+    // four wavefronts per cell, one work-group per CU (its LDS)
+    add(CHEM_MODE_TEAM, 0, 0);
+    add(CHEM_MODE_TEAM_PERSISTENT, 0, 0);
   }
-  if (N <= 16 || N > 64) {
+  if (N <= 16 || N > T4_NMAX) {
     add(CHEM_MODE_PLAIN, 64, 0);
     add(CHEM_MODE_PLAIN, 256, 0);
     add(CHEM_MODE_PERSISTENT, 64, 0);

@@ -480,6 +480,10 @@ __device__ __forceinline__ void team_lu_col(double (&A)[NMAX], int& ord, double&
     // lane KC records p (a v_writelane with a constant lane: no per-column
     // lane mask to keep live)
     asm("v_writelane_b32 %0, %1, %2" : "+v"(pv) : "s"(p), "i"(KC));
+    // keep the step's bookkeeping here: left alone, the compiler sinks the
+    // select chains of ord, rp_own and rc to their use after the last column
+    // and keeps every column's inputs live until then
+    asm volatile("" : "+v"(ord), "+v"(rp_own), "+v"(rc));
 #pragma unroll
     for (int j = KC + 1; j < NMAX; ++j) A[j] -= l * bcast(A[j], p);
     team_lu_col<NMAX, KC + 1>(A, ord, rp_own, pv, rc);

@@ -162,6 +162,49 @@ def test_full_size_adjoint_sampled(chem, ch4):
         assert g[:, c] @ v == pytest.approx(w @ dY, rel=1e-6, abs=1e-9 * np.abs(g[:, c]).sum() + 1e-300), c
 
 
+@pytest.mark.timeout(600)
+def test_differentiation_case_central_differences_64_cells(chem, ch4):
+    """The differentiation case's finite-difference check: 64 cells of its
+    distribution (the 16 with the most steps and 48 at random), gradients of
+    L1 = T_final and L2 = sum_k w_k Y_k,final along a random direction in ln A
+    against central differences (h = 1e-6) on the GPU's frozen steps, within
+    1e-5 relative (plus a floor of 3e-7 of the loss's uncancelled scale, the
+    rounding of the replays over 2h)."""
+    path, m, o = ch4
+    say("case: adjoint vs central differences, ch4 mechanism, 64 cells, dt=1e-5")
+    T, P, Y = synth.states_mixing(m, 16384, 205)
+    w = synth.loss_weights(m)
+    mech = chem.Mechanism(path)
+    ns = chem.integrate(mech, dev(T), dev(P), dev(Y), 1e-5)[3].cpu().numpy()
+    rng = np.random.default_rng(64)
+    top = np.argsort(-ns)[:16]
+    idx = np.r_[top, rng.choice(np.setdiff1d(np.arange(T.size), top), 48, replace=False)]
+    T, P, Y = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+    n = idx.size
+    T1, Y1, h1, ns, st, ck = chem.integrate(mech, dev(T), dev(P), dev(Y), 1e-5, checkpoint=True)
+    gT = torch.ones(n, dtype=torch.float64, device="cuda")
+    gY = torch.zeros((m.n_species, n), dtype=torch.float64, device="cuda")
+    g1, _, _ = chem.adjoint(mech, ck, gT, gY, per_cell=True, initial=False)
+    g2, _, _ = chem.adjoint(mech, ck, torch.zeros_like(gT), dev(np.repeat(w[:, None], n, 1)), per_cell=True,
+                            initial=False)
+    torch.cuda.synchronize()
+    off, rec = ck.export()
+    ck.close()
+    mech.close()
+    g1, g2 = g1.cpu().numpy(), g2.cpu().numpy()
+    hstep = 1e-6
+    for c in range(n):
+        hs = rec[off[c]:off[c + 1] - 1, -1].copy()
+        v = rng.normal(size=len(m.reactions))
+        Tp, Yp = o.replay(T[c], P[c], Y[:, c], hs, lnA=o.lnA + hstep * v)
+        Tm, Ym = o.replay(T[c], P[c], Y[:, c], hs, lnA=o.lnA - hstep * v)
+        dT, dY = o.tangent(T[c], P[c], Y[:, c], hs, v_lnA=v)
+        fd1 = (Tp - Tm) / (2 * hstep)
+        fd2 = w @ (Yp - Ym) / (2 * hstep)
+        assert g1[:, c] @ v == pytest.approx(fd1, rel=1e-5, abs=3e-7 * abs(dT) + 1e-300), (c, "T")
+        assert g2[:, c] @ v == pytest.approx(fd2, rel=1e-5, abs=3e-7 * np.abs(w * dY).sum() + 1e-300), (c, "wY")
+
+
 def test_cell_sum_is_deterministic_reduction(case):
     assert np.allclose(case["gsum"], case["g2"].sum(1), rtol=1e-12, atol=1e-300)
 

@@ -267,25 +267,62 @@ def test_mechanism_sizes_team_parity(chem, mech_dir, name):
         assert g[:, c] @ v == pytest.approx(dT, rel=1e-6, abs=1e-9 * np.abs(g[:, c]).sum() + 1e-300), c
 
 
-@pytest.mark.timeout(900)
-def test_large_parity(chem, large):
-    """The 111-species mechanism (N = 112) on 512 of its mixing-layer states,
-    dt = 1e-5 s: each cell takes ~50 accepted steps, so every row of the
-    112 x 112 LU and many controller decisions are compared; every cell
-    against the oracle, in the default launch."""
+@pytest.fixture(scope="module")
+def large_cells(large):
+    """512 of the 111-species mechanism's mixing-layer states (dt = 1e-5 s):
+    each takes ~50 accepted steps, so every row of the 112 x 112 LU and many
+    controller decisions are compared."""
     path, m, o = large
-    say("case: large mechanism, 512 cells, auto launch")
     T, P, Y = synth.states_mixing(m, 262144, 204)
     rng = np.random.default_rng(5)
     idx = np.unique(np.r_[rng.choice(T.size, 496, replace=False), np.argsort(-T)[:16]])
-    T, P, Y = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+    return T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+
+
+@pytest.mark.timeout(900)
+def test_large_parity(chem, large, large_cells):
+    """N = 112: every cell against the oracle in the default launch (four
+    wavefronts per cell, persistent) and the plain grid of the same kernel,
+    which must agree bit for bit; the one-cell-per-thread launch on 64 of the
+    cells."""
+    path, m, o = large
+    T, P, Y = large_cells
+    say("case: large mechanism, 512 cells, four-wavefront launches")
+    mech = chem.Mechanism(path)
+    res = {mode: run_gpu(chem, mech, T, P, Y, 1e-5, mode=mode) for mode in ("auto", "team", "team_persistent")}
+    say("case: large mechanism, 64 cells, one cell per thread")
+    th = run_gpu(chem, mech, T[:64], P[:64], np.ascontiguousarray(Y[:, :64]), 1e-5, mode="plain")
+    mech.close()
+    for k in range(5):
+        assert np.array_equal(res["team"][k], res["team_persistent"][k])
+        assert np.array_equal(res["auto"][k], res["team_persistent"][k])
+    Tg, Yg, hg, ng, sg = res["auto"]
+    assert np.all(sg == 0)
+    r, msg = parity.check_batch(o, T, P, Y, 1e-5, Tg, Yg, ng, "large 512 four-wavefront")
+    say(msg)
+    assert np.median(r["n_acc"]) > 20
+    assert np.median(np.abs(hg - r["h"]) / r["h"]) < 1e-6
+    say(parity.check_batch(o, T[:64], P[:64], np.ascontiguousarray(Y[:, :64]), 1e-5, th[0], th[1], th[3],
+                           "large 64 one-cell-per-thread")[1])
+
+
+@pytest.mark.timeout(900)
+def test_large_full_size_sampled(chem, large):
+    """The 111-species mechanism at its full size, 262,144 mixing-layer cells
+    in the default launch; 1,024 cells re-run on the oracle (the 64 with the
+    most steps and 960 at random)."""
+    path, m, o = large
+    say("case: large mechanism, 262144 cells, auto launch")
+    T, P, Y = synth.states_mixing(m, 262144, 204)
     mech = chem.Mechanism(path)
     Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-5, mode="auto")
     mech.close()
     assert np.all(sg == 0)
-    r, msg = parity.check_batch(o, T, P, Y, 1e-5, Tg, Yg, ng, "large 512")
-    say(msg)
-    assert np.median(r["n_acc"]) > 20
+    rng = np.random.default_rng(6)
+    top = np.argsort(-ng)[:64]
+    idx = np.unique(np.r_[top, rng.choice(np.setdiff1d(np.arange(T.size), top), 960, replace=False)])
+    Ts, Ps, Ys = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+    say(parity.check_batch(o, Ts, Ps, Ys, 1e-5, Tg[idx], Yg[:, idx], ng[idx], "large 1024 of 262144")[1])
 
 
 @pytest.mark.parametrize("mode", ["plain", "persistent", "team", "team_persistent"])
