@@ -168,6 +168,28 @@ int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const dou
                    const double* lnA, const chem_opts* opts, chem_ckpt_t* ckpt_out,
                    hipStream_t stream);
 
+/* chem_integrate without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and results as chem_integrate (no
+ * checkpoint), with the one-wavefront-per-cell launches only: N <= 64, mode
+ * CHEM_MODE_AUTO, CHEM_MODE_TEAM or CHEM_MODE_TEAM_PERSISTENT (AUTO and an
+ * autotuned one-cell-per-thread choice run the persistent team launch; an
+ * explicit one-cell-per-thread mode is CHEM_EUNSUPPORTED).  After a rejected
+ * step the Jacobian is evaluated again instead of reloaded (the same values,
+ * so the results equal chem_integrate's).
+ * Scratch: a fixed array in the library's device image, one per device, held
+ * until the process ends - the work-queue counter, the dispatch-order bins and
+ * the cell order, 4 MiB + 2.3 KiB: at most 1,048,576 cells per call
+ * (CHEM_EINVAL above).  Every call on a device shares that device's array, so
+ * calls that overlap on one device (on different streams, or from several
+ * threads) race and must be serialised by the caller; the counter and bins
+ * are cleared by kernels at the start of each call (no memset).
+ * Errors: CHEM_EINVAL, CHEM_EUNSUPPORTED, CHEM_EHIP.  Asynchronous on `stream`. */
+int chem_integrate_noalloc(chem_mech_t m, int64_t n_cells, const double* T_in, const double* P,
+                           const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
+                           double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
+                           const double* lnA, const chem_opts* opts, hipStream_t stream);
+
 /* Discrete adjoint of the checkpointed integration: reverse sweep over every
  * cell's accepted steps with the step sizes frozen, through the stages of the
  * transformed Rosenbrock step of Sec. 2.3 (ROS4), the state conversion of

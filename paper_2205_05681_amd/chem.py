@@ -79,7 +79,7 @@ def lib():
 EXPORTS = ("chem_opts_default", "chem_error_string", "chem_mech_load", "chem_mech_info",
            "chem_mech_free", "chem_integrate", "chem_integrate_adjoint", "chem_ckpt_free", "chem_eval",
            "chem_ckpt_records", "chem_ckpt_export", "chem_graph_create", "chem_graph_launch",
-           "chem_graph_free", "chem_autotune")
+           "chem_graph_free", "chem_autotune", "chem_integrate_noalloc")
 
 
 def error_string(code):

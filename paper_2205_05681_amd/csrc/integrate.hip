@@ -971,6 +971,16 @@ __global__ void sample_cells_kernel(int64_t ns, int64_t stride, int K, const dou
   for (int k = 0; k < K; ++k) Ys[(int64_t)k * ns + i] = Y[(int64_t)k * ldY + c];
 }
 
+// Scratch of chem_integrate_noalloc: the work-queue counter (word 0), the
+// dispatch-order bins (words 64 .. 64 + 2 ORDER_BINS) and the queue position ->
+// cell map (NOALLOC_MAX_CELLS words).  One copy per device, held until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the device.
+constexpr int64_t NOALLOC_MAX_CELLS = 1 << 20;
+constexpr size_t NOALLOC_ORDER_WORD = 64 + 2 * ORDER_BINS;
+constexpr size_t NOALLOC_WORDS = NOALLOC_ORDER_WORD + NOALLOC_MAX_CELLS;
+static __device__ __align__(256) unsigned int scratch[NOALLOC_WORDS];
+
 }  // namespace chem
 
 // ====================================================================== host side
@@ -1114,6 +1124,23 @@ bool tuned_lookup(chem_mech_t m, int64_t n, chem_opts* out) {
   return true;
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned int* g_scratch[MAX_DEVICES];   // device address of `scratch` on each device
+
+// Device address of this device's scratch array (the device must be current).
+int scratch_address(int device, unsigned int** out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (device < 0 || device >= MAX_DEVICES) return CHEM_EUNSUPPORTED;
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CHEM_EHIP;
+    g_scratch[device] = (unsigned int*)ptr;
+  }
+  *out = g_scratch[device];
+  return CHEM_OK;
+}
+
 typedef void (*TeamKernel)(IntParams, bool);
 
 // One wavefront per cell holds a state vector element per lane: N <= 64.
@@ -1185,6 +1212,10 @@ int chem_mech_load(const char* path, int device, chem_mech_t* out) {
     return CHEM_EHIP;
   }
   m->n_cu = prop.multiProcessorCount;
+  {
+    unsigned int* sp;   // set up the no-allocation entry point's scratch on this device
+    (void)scratch_address(device, &sp);
+  }
   const HostMech& h = m->host;
   // one blob, each array 256-byte aligned
   struct Part { const void* src; size_t bytes; size_t off; };
@@ -1390,6 +1421,57 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   (void)hipFree(tn);
   *ckpt_out = c;
   return CHEM_OK;
+}
+
+static int resolve_opts(chem_mech_t m, int64_t n, const chem_opts* opts, chem_opts* out);
+static int team_launch(chem_mech_t m, const chem_opts& o, IntParams p, bool persistent,
+                       unsigned int* queue, Workspace* jsave_ws, hipStream_t stream);
+static int launch_order(int64_t n, const double* T_in, unsigned int* bins, int32_t* order,
+                        hipStream_t stream);
+static bool wants_order(int32_t mode, int64_t n);
+static IntParams make_params(chem_mech_t m, const chem_opts& o, int64_t n, const double* T_in,
+                             const double* P, const double* Y_in, int64_t ldY, double* T_out,
+                             double* Y_out, double dt, double rtol, double atol, double* h_io,
+                             int32_t* n_steps, int32_t* status, const double* lnA);
+
+int chem_integrate_noalloc(chem_mech_t m, int64_t n, const double* T_in, const double* P,
+                           const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
+                           double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
+                           const double* lnA, const chem_opts* opts, hipStream_t stream) {
+  if (!m || n < 0 || n > NOALLOC_MAX_CELLS) return CHEM_EINVAL;
+  if (n > 0 && (!T_in || !P || !Y_in || !T_out || !Y_out)) return CHEM_EINVAL;
+  if (!(dt > 0) || !(rtol > 0) || !(atol >= 0) || ldY < n) return CHEM_EINVAL;
+  if (m->view.N > T4_NMAX) return CHEM_EUNSUPPORTED;
+  chem_opts o;
+  resolve_opts(m, n, opts, &o);
+  if (o.mode < CHEM_MODE_AUTO || o.mode > CHEM_MODE_TEAM_PERSISTENT) return CHEM_EINVAL;
+  if (o.mode == CHEM_MODE_PLAIN || o.mode == CHEM_MODE_PERSISTENT) {
+    // an autotuned one-cell-per-thread choice needs a workspace: use the team launch
+    if (opts && (opts->mode == CHEM_MODE_PLAIN || opts->mode == CHEM_MODE_PERSISTENT)) return CHEM_EUNSUPPORTED;
+    o.mode = CHEM_MODE_TEAM_PERSISTENT;
+  }
+  if (o.mode == CHEM_MODE_AUTO) o.mode = CHEM_MODE_TEAM_PERSISTENT;
+  if (o.max_steps <= 0 || !(o.fac_min > 0) || !(o.fac_max >= 1) || !(o.safety > 0)) return CHEM_EINVAL;
+  if (o.order != CHEM_ORDER_INDEX && o.order != CHEM_ORDER_HOT_FIRST) return CHEM_EINVAL;
+  if (o.method < 0 || o.method >= N_METHODS) return CHEM_EINVAL;
+  if (o.estimator != CHEM_EST_EMBEDDED && o.estimator != CHEM_EST_FILTERED) return CHEM_EINVAL;
+  if (o.team_waves != 0 && o.team_waves != 1 && o.team_waves != 4) return CHEM_EINVAL;
+  if ((o.team_waves == 1 && m->view.N > 64) || (o.team_waves == 4 && m->view.N <= 64)) return CHEM_EUNSUPPORTED;
+  if (o.wg_size < 0 || o.wg_size > 256 || (o.wg_size % 64) != 0) return CHEM_EINVAL;
+  if (n == 0) return CHEM_OK;
+  HIPCHECK(hipSetDevice(m->device));
+  unsigned int* sp = nullptr;
+  int rc = scratch_address(m->device, &sp);
+  if (rc) return rc;
+  IntParams p = make_params(m, o, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
+                            status, lnA);
+  if (wants_order(o.order, n)) {
+    int32_t* order = (int32_t*)(sp + NOALLOC_ORDER_WORD);
+    rc = launch_order(n, T_in, sp + 64, order, stream);
+    if (rc) return rc;
+    p.order = order;
+  }
+  return team_launch(m, o, p, o.mode == CHEM_MODE_TEAM_PERSISTENT, sp, nullptr, stream);
 }
 
 // Dispatch order of the cells (hottest first) into w->order; *order receives
