@@ -307,7 +307,10 @@ def work_precision(c, a):
     largest over cells - and GPU time per call.  States: a sample of the
     65,536 mixing-layer cells (the 64 with the most steps and the rest at
     random), dt = 1e-6 s.  Reference: the CPU oracle with RODAS4 at
-    rtol = 1e-14, atol = 1e-20 (the paper uses CVODES at 1e-15 / 1e-20)."""
+    rtol = 1e-14, atol = 1e-18 (the paper uses CVODES at 1e-15 / 1e-20; with
+    atol 1e-20 the hottest cell takes 347,169 steps, and the atol 1e-18 and
+    1e-20 references differ by 3e-5 in this norm, the FP64 rounding of such
+    long integrations - the floor of the comparison)."""
     import oracle
     np, chem, synth = c.np, c.chem, c.synth
     path, m = synth.mechanism_file("ch4", c.mech_dir)
@@ -321,9 +324,20 @@ def work_precision(c, a):
     T, P, Y = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
     log("work-precision: reference on %d cells" % idx.size)
     t0 = time.time()
-    ref = oracle.Oracle(path).integrate(T, P, Y, 1e-6, rtol=1e-14, atol=1e-20, method="rodas4")
+    ora = oracle.Oracle(path)
+    parts, threads = [], 0
+    ref_status = []
+    for s0 in range(0, idx.size, 64):
+        s = slice(s0, min(s0 + 64, idx.size))
+        ref = ora.integrate(T[s], P[s], np.ascontiguousarray(Y[:, s]), 1e-6, rtol=1e-14, atol=1e-18,
+                            method="rodas4", max_steps=10 ** 7)
+        parts.append(np.vstack([ref["T"], ref["Y"]]))
+        ref_status.append(ref["status"])
+        threads = ref["threads"]
+        log("work-precision: reference %d/%d cells, %.0f s" % (s.stop, idx.size, time.time() - t0))
     t_ref = time.time() - t0
-    yref = np.vstack([ref["T"], ref["Y"]])
+    yref = np.hstack(parts)
+    ref_ok = np.concatenate(ref_status) == 0
     Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
     pts = []
     for meth in ("ros3", "ros4", "rodas3", "rodas4"):
@@ -334,15 +348,18 @@ def work_precision(c, a):
                 r = chem.integrate(mech, Tt, Pt, Yt, 1e-6, rtol=tol, atol=tol, opts=o)
                 t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, rtol=tol, atol=tol, opts=o))
                 y = np.vstack([r[0].cpu().numpy(), r[1].cpu().numpy()])
-                E = np.sqrt((((yref - y) / (1e-10 + 1e-6 * np.abs(yref))) ** 2).sum(0))
-                pts.append({"method": meth, "estimator": est, "tol": tol, "error_norm": float(E.max()),
-                            "error_norm_median": float(np.median(E)), "ms": round(t * 1e3, 3),
+                ok = ref_ok & (r[4].cpu().numpy() == 0)
+                E = np.sqrt((((yref - y) / (1e-10 + 1e-6 * np.abs(yref))) ** 2).sum(0))[ok]
+                pts.append({"method": meth, "estimator": est, "tol": tol, "error_norm": float(E.max()) if E.size else None,
+                            "error_norm_median": float(np.median(E)) if E.size else None, "ms": round(t * 1e3, 3),
                             "failed": int((r[4] != 0).sum().item())})
             log("work-precision: %s %s done" % (meth, est))
     mech.close()
     return {"workload": "%d of the 65,536 CH4 mixing-layer cells (64 with the most steps), dt=1e-6 s" % idx.size,
-            "reference": "oracle RODAS4, rtol 1e-14, atol 1e-20, %.1f s on %d threads" % (t_ref, ref["threads"]),
-            "norm": "max over cells of the 2-norm over (T, Y) of |y_ref - y| / (1e-10 + 1e-6 |y_ref|)",
+            "reference": "oracle RODAS4, rtol 1e-14, atol 1e-18, %.1f s on %d threads; %d of %d cells "
+                         "finished" % (t_ref, threads, int(ref_ok.sum()), ref_ok.size),
+            "norm": "max over cells of the 2-norm over (T, Y) of |y_ref - y| / (1e-10 + 1e-6 |y_ref|); "
+                    "cells a solver did not finish are counted in 'failed' and left out of the norm",
             "points": pts}
 
 
@@ -415,7 +432,9 @@ def main():
                     help="first run one 256 MiB device-to-device copy (reference for HBM byte counters)")
     ap.add_argument("--work-precision", default="",
                     help="run only the work-precision sweep and write its JSON to this file")
-    ap.add_argument("--wp-cells", type=int, default=2048)
+    ap.add_argument("--wp-cells", type=int, default=256)
+    ap.add_argument("--only", default="", help="run only this leg (mixing, methods, large, small, adjoint) "
+                                               "and print its JSON (for profiling one workload)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU; --gpus %d is not supported "
@@ -441,6 +460,10 @@ def main():
         with open(a.work_precision, "w") as f:
             json.dump(wp, f)
         print(json.dumps({"work_precision": a.work_precision, "points": len(wp["points"])}), flush=True)
+        return
+    if a.only:
+        fn = {"mixing": mixing, "methods": methods, "large": large, "small": small, "adjoint": adjoint_cost}[a.only]
+        print(json.dumps({a.only: fn(c, a)}), flush=True)
         return
     head, head_data = headline(c, a)
     skip = set(a.skip.split(",")) if a.skip else set()

@@ -347,7 +347,6 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
   const int lane = threadIdx.x;
   TeamLds L;
   L.bind(lds_raw, N);
-  double* const jsv = p.jsave ? p.jsave + (int64_t)blockIdx.x * N * N : nullptr;
   int64_t q;   // queue position
   if (PERSISTENT) {
     unsigned c0 = 0;
@@ -387,28 +386,18 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       }
       ++attempts;
       const double hs = fmin(h, rem);
-      // J(Phi) into LDS: evaluated after an accepted step; after a rejection
-      // (same Phi, the LU has overwritten J) reloaded from this work-group's
-      // saved copy, or evaluated again where there is none
-      if (need_jac || !jsv) {
+      // J(Phi) into LDS after an accepted step; a rejected step keeps it
+      // (same Phi; the factors live in registers, J is not overwritten)
+      if (need_jac) {
         f1 = team_rhs_jac(M, P, phi, L, p.lnA);
         need_jac = false;
-        if (jsv && lane < N)
-          for (int i = 0; i < N; ++i) jsv[i * N + lane] = L.J[i * ldj + lane];
-      } else {
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");   // own stores done, L1 invalidated
-        if (lane < N)
-          for (int i = 0; i < N; ++i) L.J[i * ldj + lane] = jsv[i * N + lane];
-        wsync();
       }
-      // factors of M = I/(h gamma) - J over J
-      int perm;
-      double rdiag;
+      // factors of M = I/(h gamma) - J, row i in lane i's registers
+      RegLU<NMAX> F;
       const RosTable& R = p.tab;
-      const int rc = team_lu<NMAX>(L.J, ldj, N, 1.0 / (hs * R.gamma), perm, rdiag);
+      const int rc = team_lu_reg<NMAX>(L.J, ldj, N, 1.0 / (hs * R.gamma), F);
       double err = 0.0, ynew = 0.0;
       if (rc == 0) {
-        const double* F = L.J;
         // stage i: f at phi + sum_{j<i} a_ij u_j (or the previous stage's f
         // when the argument is the same), then M u_i = f + sum_{j<i} (c_ij/h)
         // u_j.  Lane i keeps element i of every stage vector in the LDS stage
@@ -424,7 +413,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
           }
           double r = fs;
           for (int j = 0; j < i; ++j) r += (R.c[i][j] / hs) * L.ust[64 * j + lane];
-          L.ust[64 * i + lane] = team_solve<NMAX>(F, ldj, N, perm, rdiag, r);
+          L.ust[64 * i + lane] = team_solve_reg<NMAX>(F, N, r);
         }
         double e = 0.0;
         ynew = phi;
@@ -434,7 +423,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
           e += R.e[j] * uj;
         }
         if (p.estimator == CHEM_EST_FILTERED)
-          e = team_solve<NMAX>(F, ldj, N, perm, rdiag, e) / (hs * R.gamma);
+          e = team_solve_reg<NMAX>(F, N, e) / (hs * R.gamma);
         const double sc = p.atol + p.rtol * fmax(fabs(phi), fabs(ynew));
         const double r = (lane < N) ? e / sc : 0.0;
         err = sqrt(wave_sum(r * r) / N);
@@ -1562,7 +1551,7 @@ static int team_launch(chem_mech_t m, const chem_opts& o, IntParams p, bool pers
     if (o.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, o.waves_per_cu * 64 / threads));
     if (per_cu < 1) per_cu = 1;
     grid = (unsigned)std::min<int64_t>((int64_t)m->n_cu * per_cu, p.n);
-    if (jsave_ws) {
+    if (jsave_ws && four) {   // the one-wavefront kernel keeps J in LDS across a rejection
       std::lock_guard<std::mutex> g(m->mu);
       const int rc = grow((void**)&jsave_ws->jsave, &jsave_ws->jsave_bytes,
                           (size_t)grid * N * N * sizeof(double));

@@ -536,6 +536,75 @@ __device__ __forceinline__ int team_lu(double* __restrict__ F, int ldj, int N, d
   return 0;
 }
 
+// Factors of M held in registers: lane i keeps row i of M after elimination -
+// the multipliers (row ord of L) in the columns before ord, row ord of U from
+// column ord on, where ord is the step at which this row was the pivot.
+// Lanes past N hold identity rows pivoted at their own index, lanes past NMAX
+// zero rows that never pivot.
+template <int NMAX>
+struct RegLU {
+  double A[NMAX];
+  int ord;        // pivot step of this lane's row
+  int pv;         // lane k: the lane (row of M) pivoted at step k
+  double rown;    // 1 / (this row's pivot)
+  double rdg;     // lane k: 1 / U_kk
+};
+
+// The elimination of team_lu, with the factors left in registers and J in LDS
+// untouched, so that a rejected step can form M again from the same J.
+// Returns 0, 1 (zero pivot) or 2 (non-finite pivot column).
+template <int NMAX>
+__device__ __forceinline__ int team_lu_reg(const double* __restrict__ J, int ldj, int N, double d,
+                                           RegLU<NMAX>& F) {
+  const int lane = threadIdx.x;
+  const bool own = lane < N;
+  const double* row = J + (own ? lane : 0) * ldj;
+  const int jn = own ? N : 0;
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j) {
+    const double f = (j < jn) ? row[j] : 0.0;
+    const double dj = ((j == lane) & (j < jn)) ? d : 0.0;
+    F.A[j] = ((lane >= N) & (j == lane)) ? 1.0 : dj - f;
+  }
+  F.ord = lane < NMAX ? -1 : NMAX;
+  F.rown = 0.0;
+  F.pv = lane;
+  int rc = 0;
+  team_lu_col<NMAX, 0>(F.A, F.ord, F.rown, F.pv, rc);
+  F.rdg = gather(F.rown, F.pv);
+  return rc;
+}
+
+// Solve M x = b with the register factors of team_lu_reg.  b is
+// lane-distributed by equation (element i in lane i = row i of M; lanes >= N
+// hold 0) and so are the factor rows, so no permutation is applied up front.
+// Forward, over the pivot steps k: y_k is the current value in the pivot lane
+// p_k, and the rows pivoted later subtract L_(ord,k) y_k.  Backward, from the
+// last step: x_k = z(p_k) / U_kk, and the rows pivoted earlier subtract
+// U_(ord,k) x_k.  Every step is unrolled, so the factor entry is a register;
+// p_k and 1/U_kk are read with constant lanes.  The result x_k is gathered
+// into lane k.
+template <int NMAX>
+__device__ __forceinline__ double team_solve_reg(const RegLU<NMAX>& F, int N, double b) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NMAX - 1; ++k) {
+    const int p = __builtin_amdgcn_readlane(F.pv, k);
+    const double yk = bcast(b, p);
+    const double l = (F.ord > k) ? F.A[k] : 0.0;
+    b -= l * yk;
+  }
+#pragma unroll
+  for (int k = NMAX - 1; k > 0; --k) {
+    const int p = __builtin_amdgcn_readlane(F.pv, k);
+    const double xk = bcast(b, p) * bcast(F.rdg, k);
+    const double u = (F.ord < k) ? F.A[k] : 0.0;
+    b -= u * xk;
+  }
+  const double x = gather(b * F.rown, F.pv);
+  return lane < N ? x : 0.0;
+}
+
 // Solve M x = b with the factors of team_lu (row k of F holds row k of L and
 // of U in pivot order; perm and rdiag as returned).  b and x are
 // lane-distributed (element i in lane i; lanes >= N hold 0).  Every column
