@@ -47,8 +47,8 @@ extern "C" {
 #define CHEM_ENOMEM (-4)       /* device allocation failed */
 #define CHEM_EUNSUPPORTED (-5) /* mechanism larger than the compiled limits, or a method the
                                   call does not support (the adjoint is ROS4 only) */
-#define CHEM_ENONDET (-6)      /* checkpointed integration: the recording pass took other
-                                  steps than the counting pass (a non-deterministic launch) */
+#define CHEM_ENONDET (-6)      /* checkpointed integration: a repeated pass took other
+                                  steps than the first (a non-deterministic launch) */
 
 /* ---- per-cell outcome (status[cell]) ----------------------------------- */
 #define CHEM_CELL_OK 0
@@ -153,10 +153,12 @@ void chem_mech_free(chem_mech_t m);
  *   ckpt_out  nullable; non-null records every accepted step (state and h;
  *             the adjoint recomputes the stage vectors) for
  *             chem_integrate_adjoint; *ckpt_out receives a new checkpoint
- *             that the caller frees.  This runs the integration twice (a
- *             counting pass sizes the record arena, both passes with the same
- *             resolved options) and synchronises the stream; the counting pass
- *             writes only library scratch
+ *             that the caller frees.  One pass records into an arena sized
+ *             from the handle's previous checkpointed call (records per cell,
+ *             at most a quarter of the free device memory); if it fills up,
+ *             the call runs once more with the exact size from that pass's
+ *             step counts (same resolved options, from copies of the inputs).
+ *             Synchronises the stream
  * All pointers are device pointers owned by the caller.  The library uses a
  * per-(handle, stream) workspace that it allocates on first use and grows.
  * Errors: CHEM_EINVAL (null pointer, n < 0, dt <= 0, rtol <= 0, atol < 0,
@@ -171,12 +173,13 @@ int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const dou
 /* chem_integrate without any device allocation, for callers that cannot
  * allocate: code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc.  Same arguments and results as chem_integrate (no
- * checkpoint), with the one-wavefront-per-cell launches only: N <= 64, mode
- * CHEM_MODE_AUTO, CHEM_MODE_TEAM or CHEM_MODE_TEAM_PERSISTENT (AUTO and an
- * autotuned one-cell-per-thread choice run the persistent team launch; an
- * explicit one-cell-per-thread mode is CHEM_EUNSUPPORTED).  After a rejected
- * step the Jacobian is evaluated again instead of reloaded (the same values,
- * so the results equal chem_integrate's).
+ * checkpoint), with the team launches only (one or four wavefronts per cell,
+ * N <= 128), mode CHEM_MODE_AUTO, CHEM_MODE_TEAM or CHEM_MODE_TEAM_PERSISTENT
+ * (AUTO and an autotuned one-cell-per-thread choice run the persistent team
+ * launch; an explicit one-cell-per-thread mode is CHEM_EUNSUPPORTED).  With
+ * four wavefronts per cell (64 < N <= 128) a rejected step evaluates the
+ * Jacobian again instead of reloading a saved copy (the same values, so the
+ * results equal chem_integrate's).
  * Scratch: a fixed array in the library's device image, one per device, held
  * until the process ends - the work-queue counter, the dispatch-order bins and
  * the cell order, 4 MiB + 2.3 KiB: at most 1,048,576 cells per call
@@ -200,10 +203,10 @@ int chem_integrate_noalloc(chem_mech_t m, int64_t n_cells, const double* T_in, c
  *   g_lnA               [Nr] dL/d ln A summed over cells (per_cell = 0) or
  *                       [Nr][n] per cell (per_cell = 1), overwritten
  *   gT0[n], gY0[K][ldY] nullable: dL/dT_in, dL/dY_in
- * One wavefront per cell: needs N <= 64 and the per-cell LDS (two N x (N+1)
- * matrices, dual vectors and Nr accumulators) within the device's LDS per
- * work-group (160 KiB on MI355X), and a checkpoint taken with ROS4, else
- * CHEM_EUNSUPPORTED.  The sum over cells is taken in a fixed order.
+ * One wavefront per cell: needs N <= 64 and the per-cell LDS (one N x (N+1)
+ * matrix, the vectors in doubles and in dual numbers, and Nr accumulators)
+ * within the device's LDS per work-group (160 KiB on MI355X), and a
+ * checkpoint taken with ROS4, else CHEM_EUNSUPPORTED.  The sum over cells is taken in a fixed order.
  * Errors: CHEM_EINVAL, CHEM_EHIP, CHEM_ENOMEM, CHEM_EUNSUPPORTED.
  * Synchronises the stream when per_cell = 0 (it frees the per-cell scratch). */
 int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, const double* gY,

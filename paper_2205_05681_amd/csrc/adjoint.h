@@ -18,8 +18,10 @@
 //   stage 1: mu1;  Phibar += J(Phi)^T mu1;  lnAbar += f_p(Phi)^T mu1
 //   through M(Phi): Phibar += sum_i d/de [J(Phi + e u_i)^T mu_i],
 //                   lnAbar += sum_i d/de [f_p(Phi + e u_i)^T mu_i]
-// The last two terms are directional derivatives of the Jacobian and of
-// f_p^T mu, evaluated exactly with forward-mode dual numbers.
+// J(Y)^T mu and f_p(Y)^T mu are vector-Jacobian products (team_vjp: reverse
+// mode through f, no Jacobian formed); the last two terms are their
+// directional derivatives, evaluated exactly by running team_vjp on dual
+// numbers.
 // f_p^T mu for reaction j: ln A_j scales the whole rate constant (both
 // directions, both falloff limits), so d f / d ln A_j = (d f / d q_j) q_j and
 //   (f_p^T mu)_j = q_j sum_k nu_kj wbar_k,
@@ -81,101 +83,157 @@ __device__ __forceinline__ double team_solve_t(const double* __restrict__ F, int
   return gather(b, invperm);
 }
 
-// (J^T mu)_c for the Jacobian held in LDS (lanes over columns); rows are read
-// eight at a time (a loop over blocks of eight rows up to NMAX >= N, with the
-// rows past N masked), so that eight loads are in flight at once.
-template <int NMAX>
-__device__ __forceinline__ double team_jt_mu(const double* __restrict__ J, int ldj, int N, double mu) {
-  const int lane = threadIdx.x;
-  const double* col = J + lane;
-  double acc = 0.0;
-#pragma unroll 1
-  for (int r0 = 0; r0 < NMAX; r0 += 8) {
-    double e[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = r0 + t;
-      const double v = col[r * ldj];
-      e[t] = ((lane < N) & (r < N)) ? v : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = r0 + t;
-      const double m = (r < N) ? bcast(mu, r) : 0.0;
-      acc += e[t] * m;
-    }
-  }
-  return acc;
-}
-
-// (dJ^T mu)_c and (J^T mu)_c for a dual Jacobian (value and directional derivative).
-template <int NMAX>
-__device__ __forceinline__ void team_jt_mu_dual(const Dd* __restrict__ J, int ldj, int N, double mu,
-                                                double& val_part, double& der_part) {
-  const int lane = threadIdx.x;
-  const Dd* col = J + lane;
-  double a = 0.0, b = 0.0;
-#pragma unroll 1
-  for (int r0 = 0; r0 < NMAX; r0 += 8) {
-    double ev[8], ed[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = r0 + t;
-      const Dd e = col[r * ldj];
-      const bool on = (lane < N) & (r < N);
-      ev[t] = on ? e.v : 0.0;
-      ed[t] = on ? e.d : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = r0 + t;
-      const double m = (r < N) ? bcast(mu, r) : 0.0;
-      a += ev[t] * m;
-      b += ed[t] * m;
-    }
-  }
-  val_part = a;
-  der_part = b;
-}
-
 __device__ __forceinline__ double der(double) { return 0.0; }
 __device__ __forceinline__ double der(Dd c) { return c.d; }
+__device__ __forceinline__ Dd gather(Dd v, int src) { return Dd{gather(v.v, src), gather(v.d, src)}; }
 
-// Adds (f_p(y)^T mu)_j (if add_value) and its derivative along the dual part
-// of y to pbar[j] (LDS, Nr entries; lane j mod 64 owns reaction j).
+// J(y)^T mu and f_p(y)^T mu (added to pbar) without forming J: reverse mode
+// through f.  With G = mu^T f,
+//   f_T = Tdot = -num/D,  num = sum_k h_k wdot_k,  D = sum_k C_k cp_k,
+//   f_V = V (Tdot/T + (R T/P) W),  W = sum_k wdot_k,  f_(n_k) = V wdot_k,
+//   wdot_k = sum_j nu_kj q_j(T, C),
+//   C_k = n_k / V (k < K-1),  C_b = P/(R T) - sum_(k<K-1) C_k:
+// * wbar_k = dG/dwdot_k (as in the comment at the top) and qbar_j =
+//   sum_k nu_kj wbar_k; (f_p^T mu)_j = q_j qbar_j;
+// * through the rates: Cbar_m += qbar_j dq_j/dC_m (the reaction's species
+//   slots, and beta_j alpha_jm through [M]), Tbar += qbar_j dq_j/dT;
+// * directly: with Tdbar = dG/dTdot = mu_T + mu_V V/T,
+//   Tbar += Tdbar (-(sum cp_k wdot_k) - Tdot dD/dT)/D + mu_V V (-Tdot/T^2 + R W/P),
+//   Cbar_k += Tdbar (-Tdot/D) cp_k,
+//   Vbar = mu_V (Tdot/T + (R T/P) W) + sum_(k<K-1) mu_(n_k) wdot_k;
+// * through the closure: nbar_k = (Cbar_k - Cbar_b)/V,
+//   Vbar -= sum_(k<K-1) (Cbar_k - Cbar_b) C_k / V,  Tbar -= Cbar_b P/(R T^2).
+// S = Dd gives, in the dual part, the derivative of both products along the
+// dual part of y (mu is fixed).  Returns ybar lane-distributed (T, V, n_k);
+// pbar[j] gets (add_value ? value : 0) + derivative.
 template <class S>
-__device__ void team_pbar(const MechView& M, double P, S y, double mu, TeamLdsT<S>& L,
-                          const double* __restrict__ lnA, double* __restrict__ pbar, bool add_value) {
+__device__ S team_vjp(const MechView& M, double P, S y, double mu, TeamLdsT<S>& L,
+                      const double* __restrict__ lnA, double* __restrict__ pbar, bool add_value) {
   const int lane = threadIdx.x;
-  const int K = M.K;
-  S T, V, ctot;
-  team_state<S>(M, P, y, L, T, V, ctot, (S*)nullptr);
+  const int K = M.K, N = M.N;
+  S T, V, ctot, sdcp;
+  team_state<S>(M, P, y, L, T, V, ctot, &sdcp);
   S den = sc<S>(0.0);
   if (lane < K) den = L.conc[lane] * L.cpr[lane] * RU;
   den = wave_sum(den);
   const double muT = bcast(mu, 0), muV = bcast(mu, 1);
   const double mun = gather(mu, lane + 2 < 64 ? lane + 2 : 0);
+  const S RTP = RU * T / P;
   if (lane < K) {
     const S Hk = L.hrt[lane] * RU * T;
-    S wb = muT * (-Hk / den) + muV * V * (-Hk / (den * T) + RU * T / P);
+    S wb = muT * (-Hk / den) + muV * V * (-Hk / (den * T) + RTP);
     if (lane < K - 1) wb += mun * V;
-    L.wdot[lane] = wb;
+    L.tb[lane] = wb;             // wbar_k
+    L.wdot[lane] = sc<S>(0.0);
+    L.gb[lane] = sc<S>(0.0);     // Cbar_k through the rates
   }
   wsync();
   const S lnT = log(T), iT = 1.0 / T;
+  S tacc = sc<S>(0.0), bacc = sc<S>(0.0);   // this lane's sums of qbar dq/dT and qbar beta
+  S* const dummy = L.dwdT + lane;           // target of the updates of unused slots
   for (int j = lane; j < M.Nr; j += 64) {
     const RateOutT<S> r = reaction_rate(M, j, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
-                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, lnA, false);
+                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, lnA, true);
     const int32_t* info = M.rinfo + 8 * j;
     const int32_t* sp = M.rspec + 6 * j;
     const int32_t* nu = M.rnu + 6 * j;
-    S s = sc<S>(0.0);
-    for (int i = 0; i < info[1]; ++i) s -= (double)nu[i] * L.wdot[sp[i]];
-    for (int i = 0; i < info[2]; ++i) s += (double)nu[3 + i] * L.wdot[sp[3 + i]];
-    const S c = r.q * s;
+    const int nr = info[1], np = info[2];
+    int ks[6], nus[6];
+    bool on[6];
+    S cs[6], ws[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      on[q] = (q < 3) ? (q < nr) : (q - 3 < np);
+      ks[q] = sp[q];              // unused slots hold species 0 and coefficient 0
+      nus[q] = nu[q];
+      cs[q] = L.conc[ks[q]];
+      ws[q] = L.tb[ks[q]];
+    }
+    // qbar: reactants, then products, in slot order
+    S qb = sc<S>(0.0);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double v = (q < 3) ? -(double)nus[q] : (double)nus[q];
+      if (on[q]) qb += v * ws[q];
+    }
+    const S c = r.q * qb;
     pbar[j] += (add_value ? val(c) : 0.0) + der(c);
+    // d q / d C of slot q, as in team_rhs_jac
+    S dq[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int s0 = q < 3 ? 0 : 3;
+      S d = (q < 3) ? r.kf : r.kr;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const int v = (s0 + l == q) ? nus[s0 + l] - 1 : nus[s0 + l];
+        const S cc = cs[s0 + l];
+        d = (v >= 1) ? d * cc : d;
+        d = (v >= 2) ? d * cc : d;
+        d = (v >= 3) ? d * cc : d;
+      }
+      dq[q] = d * (double)(q < 3 ? nus[q] : -nus[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
+      lds_add(on[q] ? &L.wdot[ks[q]] : dummy, vk * r.q);
+      lds_add(on[q] ? &L.gb[ks[q]] : dummy, qb * dq[q]);
+    }
+    tacc += qb * (r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT);
+    if (info[0] != RX_ELEM) {
+      // [M] = sum C + sum (alpha - 1) C: the uniform part summed per lane, the
+      // listed efficiencies scattered (the first four read together)
+      const S qbb = qb * r.beta;
+      bacc += qbb;
+      const int e0 = info[3], e1 = info[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int e = (e0 + t < e1) ? e0 + t : e0;
+        const int m = M.eff_idx[e];
+        const double am1 = M.eff_am1[e];
+        lds_add((e0 + t < e1) ? &L.gb[m] : dummy, qbb * am1);
+      }
+      for (int e = e0 + 4; e < e1; ++e) lds_add(&L.gb[M.eff_idx[e]], qbb * M.eff_am1[e]);
+    }
   }
   wsync();
+  S num = sc<S>(0.0), cpw = sc<S>(0.0), W = sc<S>(0.0), muw = sc<S>(0.0);
+  if (lane < K) {
+    const S w = L.wdot[lane];
+    num = L.hrt[lane] * RU * T * w;
+    cpw = L.cpr[lane] * RU * w;
+    W = w;
+    if (lane < K - 1) muw = mun * w;
+  }
+  num = wave_sum(num);
+  cpw = wave_sum(cpw);
+  W = wave_sum(W);
+  muw = wave_sum(muw);
+  tacc = wave_sum(tacc);
+  bacc = wave_sum(bacc);
+  const S Tdot = -num / den;
+  const S Tdb = muT + muV * V * iT;
+  S Tb = tacc + Tdb * (-(cpw + Tdot * (sdcp * RU)) / den) + muV * V * (-Tdot * iT * iT + RU * W / P);
+  S Vb = muV * (Tdot * iT + RTP * W) + muw;
+  S cb = sc<S>(0.0);
+  if (lane < K) cb = L.gb[lane] + bacc + Tdb * (-Tdot / den) * (L.cpr[lane] * RU);
+  const S cbb = bcast(cb, K - 1);
+  S nb = sc<S>(0.0), vp = sc<S>(0.0);
+  if (lane < K - 1) {
+    const S d = cb - cbb;
+    nb = d / V;
+    vp = d * L.conc[lane];
+  }
+  Vb -= wave_sum(vp) / V;
+  Tb += cbb * (-P / (RU * T * T));
+  const S nsh = gather(nb, lane >= 2 ? lane - 2 : 0);
+  S out = sc<S>(0.0);
+  if (lane == 0) out = Tb;
+  if (lane == 1) out = Vb;
+  if (lane >= 2 && lane < N) out = nsh;
+  wsync();
+  return out;
 }
 
 }  // namespace chem

@@ -62,11 +62,43 @@ struct IntParams {
   const int32_t* order;        // nullable: queue position -> cell
   double* jsave;               // nullable: per work-group copy of J, [grid][N][N]
   unsigned long long* stats;   // nullable: attempts, accepted, rejected
-  // adjoint checkpoint (nullable): per cell, accepted (Phi_n, h) records
-  double* ck_data;          // [rec][N+1] per record, cell-major blocks
-  const int64_t* ck_off;    // [n+1] record offsets per cell
-  int32_t* ck_count;        // [n] steps counted (pass 1) or written (pass 2)
+  // adjoint checkpoint (ck_arena nullable): the (Phi_n, h_n) record of every
+  // accepted step, in chunks of CK_CHUNK records claimed from a counter as a
+  // cell needs them; a cell's chunks are linked backwards
+  double* ck_arena;               // [ck_cap][CK_CHUNK][N+1]
+  int64_t* ck_prev;               // [ck_cap] the cell's previous chunk, -1 for its first
+  unsigned long long* ck_used;    // chunks claimed (past ck_cap: the arena overflowed)
+  int64_t ck_cap;
+  int64_t* ck_head;               // [n] chunk of the cell's last record (-1: none, -2: overflow)
+  double* ck_final;               // [n][N+1] final Phi
+  int32_t* ck_count;              // [n] accepted steps
 };
+
+constexpr int CK_CHUNK = 16;
+
+// A new chunk for a cell whose current chunk is cur; -2 once the arena is full
+// (the cell records nothing more and the host repeats the call with room).
+__device__ __forceinline__ int64_t ck_claim(const IntParams& p, int64_t cur) {
+  const unsigned long long c = atomicAdd(p.ck_used, 1ull);
+  if (c >= (unsigned long long)p.ck_cap) return -2;
+  p.ck_prev[c] = cur;
+  return (int64_t)c;
+}
+
+// The chunk for record `accepted` of a cell (claimed by the calling lane when
+// the record opens a chunk).
+__device__ __forceinline__ int64_t ck_chunk_for(const IntParams& p, int64_t cur, int accepted) {
+  if (cur == -2) return -2;
+  return (accepted % CK_CHUNK == 0) ? ck_claim(p, cur) : cur;
+}
+
+// Wave-uniform chunk: lane 0 claims, every lane takes its answer.
+__device__ __forceinline__ int64_t ck_chunk_wave(const IntParams& p, int64_t cur, int accepted) {
+  int64_t c = cur;
+  if (threadIdx.x % 64 == 0) c = ck_chunk_for(p, cur, accepted);
+  const int lo = __shfl((int)(c & 0xffffffff), 0, 64), hi = __shfl((int)(c >> 32), 0, 64);
+  return (int64_t)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
 
 // ------------------------------------------------------------------ per-lane linear algebra
 // In-place LU with partial pivoting of the N x N matrix A (row-major, lane
@@ -184,7 +216,7 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
   double P = 0, h = 0, rem = 0;
   int attempts = 0, accepted = 0, bad = 0, status = 0;
   bool last_rej = false, need_jac = true, done = false;
-  int64_t ck_rec = 0;
+  int64_t ck_chunk = -1;
 
   auto init = [&](int64_t c) {
     P = p.P[c];
@@ -198,13 +230,14 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
     need_jac = true;
     done = !(T >= p.T_cut);     // T_cut = 0 integrates every cell (NaN T included)
     if (p.T_cut <= 0.0) done = false;
-    ck_rec = p.ck_off ? p.ck_off[c] : 0;
+    ck_chunk = -1;
   };
   auto finish = [&](int64_t c) {
-    if (p.ck_data) {
-      double* rec = p.ck_data + (p.ck_off[c + 1] - 1) * (int64_t)(N + 1);
-      for (int i = 0; i < N; ++i) rec[i] = phi[i];
-      rec[N] = 0.0;
+    if (p.ck_arena) {
+      double* fin = p.ck_final + c * (int64_t)(N + 1);
+      for (int i = 0; i < N; ++i) fin[i] = phi[i];
+      fin[N] = 0.0;
+      p.ck_head[c] = ck_chunk;
     }
     double T;
     from_phi(M, P, phi, p.Y_out, p.ldY, c, &T);
@@ -300,11 +333,13 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
         bad = 0;
         double fac = (err > 0.0) ? p.safety * pow(err, -1.0 / p.tab.elo) : p.fac_max;
         if (err <= 1.0) {
-          // (a record slot exists for every step the counting pass saw)
-          if (p.ck_data && ck_rec + accepted < p.ck_off[cell + 1] - 1) {
-            double* rec = p.ck_data + (ck_rec + accepted) * (int64_t)(N + 1);
-            for (int i = 0; i < N; ++i) rec[i] = phi[i];
-            rec[N] = hs;
+          if (p.ck_arena) {
+            ck_chunk = ck_chunk_for(p, ck_chunk, accepted);
+            if (ck_chunk >= 0) {
+              double* rec = p.ck_arena + (ck_chunk * CK_CHUNK + accepted % CK_CHUNK) * (int64_t)(N + 1);
+              for (int i = 0; i < N; ++i) rec[i] = phi[i];
+              rec[N] = hs;
+            }
           }
           for (int i = 0; i < N; ++i) phi[i] = ynew[i];
           rem -= hs;
@@ -373,7 +408,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
     int attempts = 0, accepted = 0, bad = 0, status = 0;
     bool last_rej = false, need_jac = true;   // need_jac: Phi changed since J was evaluated
     bool done = (p.T_cut > 0.0) && !(T0 >= p.T_cut);
-    const int64_t ck_rec = p.ck_off ? p.ck_off[cell] : 0;
+    int64_t ck_chunk = -1;
     double f1 = 0.0;
     while (!done) {
       if (attempts >= p.max_steps) {
@@ -440,11 +475,13 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       bad = 0;
       double fac = (err > 0.0) ? p.safety * pow(err, -1.0 / p.tab.elo) : p.fac_max;
       if (err <= 1.0) {
-        // (a record slot exists for every step the counting pass saw)
-        if (p.ck_data && ck_rec + accepted < p.ck_off[cell + 1] - 1) {
-          double* rec = p.ck_data + (ck_rec + accepted) * (int64_t)(N + 1);
-          if (lane < N) rec[lane] = phi;
-          if (lane == 0) rec[N] = hs;
+        if (p.ck_arena) {
+          ck_chunk = ck_chunk_wave(p, ck_chunk, accepted);
+          if (ck_chunk >= 0) {
+            double* rec = p.ck_arena + (ck_chunk * CK_CHUNK + accepted % CK_CHUNK) * (int64_t)(N + 1);
+            if (lane < N) rec[lane] = phi;
+            if (lane == 0) rec[N] = hs;
+          }
         }
         phi = ynew;
         need_jac = true;
@@ -461,10 +498,13 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
         h = hs * fac;
       }
     }
-    if (p.ck_data) {
-      double* rec = p.ck_data + (p.ck_off[cell + 1] - 1) * (int64_t)(N + 1);
-      if (lane < N) rec[lane] = phi;
-      if (lane == 0) rec[N] = 0.0;
+    if (p.ck_arena) {
+      double* fin = p.ck_final + cell * (int64_t)(N + 1);
+      if (lane < N) fin[lane] = phi;
+      if (lane == 0) {
+        fin[N] = 0.0;
+        p.ck_head[cell] = ck_chunk;
+      }
     }
     // ---- output conversion: n_K from the ideal-gas closure, Y_k = n_k W_k / mass
     {
@@ -544,7 +584,7 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
     int attempts = 0, accepted = 0, bad = 0, status = 0;
     bool last_rej = false, need_jac = true;
     bool done = (p.T_cut > 0.0) && !(T0 >= p.T_cut);
-    const int64_t ck_rec = p.ck_off ? p.ck_off[cell] : 0;
+    int64_t ck_chunk = -1;   // kept by wavefront 0, which writes the records
     V2 f1{0.0, 0.0};
     while (!done) {
       if (attempts >= p.max_steps) {
@@ -626,11 +666,14 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
       bad = 0;
       double fac = (err > 0.0) ? p.safety * pow(err, -1.0 / p.tab.elo) : p.fac_max;
       if (err <= 1.0) {
-        if (p.ck_data && ck_rec + accepted < p.ck_off[cell + 1] - 1 && w == 0) {
-          double* rec = p.ck_data + (ck_rec + accepted) * (int64_t)(N + 1);
-          rec[lane] = phi.a;
-          if (64 + lane < N) rec[64 + lane] = phi.b;
-          if (lane == 0) rec[N] = hs;
+        if (p.ck_arena && w == 0) {
+          ck_chunk = ck_chunk_wave(p, ck_chunk, accepted);
+          if (ck_chunk >= 0) {
+            double* rec = p.ck_arena + (ck_chunk * CK_CHUNK + accepted % CK_CHUNK) * (int64_t)(N + 1);
+            rec[lane] = phi.a;
+            if (64 + lane < N) rec[64 + lane] = phi.b;
+            if (lane == 0) rec[N] = hs;
+          }
         }
         phi = ynew;
         need_jac = true;
@@ -648,11 +691,14 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
       }
     }
     if (w == 0) {
-      if (p.ck_data) {
-        double* rec = p.ck_data + (p.ck_off[cell + 1] - 1) * (int64_t)(N + 1);
-        rec[lane] = phi.a;
-        if (64 + lane < N) rec[64 + lane] = phi.b;
-        if (lane == 0) rec[N] = 0.0;
+      if (p.ck_arena) {
+        double* fin = p.ck_final + cell * (int64_t)(N + 1);
+        fin[lane] = phi.a;
+        if (64 + lane < N) fin[64 + lane] = phi.b;
+        if (lane == 0) {
+          fin[N] = 0.0;
+          p.ck_head[cell] = ck_chunk;
+        }
       }
       // ---- output conversion: n_K from the ideal-gas closure, Y_k = n_k W_k / mass
       const double T = v2_get(phi, 0), V = v2_get(phi, 1);
@@ -699,8 +745,11 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
 struct AdjParams {
   MechView M;
   int64_t n;
-  const double* ck_data;   // per cell: accepted (Phi_n, h_n) records, then the final state
-  const int64_t* ck_off;   // [n + 1]
+  const double* ck_arena;  // the checkpoint's record chunks (as in IntParams)
+  const int64_t* ck_prev;
+  const int64_t* ck_head;
+  const double* ck_final;
+  const int32_t* ck_count;
   const int32_t* order;    // [n] work-group -> cell
   const double* P;         // [n]
   const double* T0;        // [n] initial state (copy)
@@ -720,26 +769,27 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
   const MechView& M = a.M;
   const int N = M.N, K = M.K, ldj = N + 1;
   const int lane = threadIdx.x;
-  const size_t mat = (size_t)N * ldj;
-  double* vb = lds_raw + 2 * mat;
-  int* plane = (int*)(vb + 2 * TeamLdsT<double>::vec_elems(N));
-  double* pbar = vb + 2 * TeamLdsT<double>::vec_elems(N) + 32;   // [Nr] d L / d ln A of this cell
-  TeamLdsT<double> LA, LB;
+  // LDS: J and its factors, the vector block (doubles), the vector block of
+  // the dual products, the pivot staging, this cell's d L / d ln A
+  const size_t mat = (size_t)N * ldj, ve = TeamLdsT<double>::vec_elems(N);
+  double* vb = lds_raw + mat;
+  Dd* vbd = (Dd*)(vb + ve);
+  int* plane = (int*)(vb + 3 * ve);
+  double* pbar = vb + 3 * ve + 32;   // [Nr]
+  TeamLdsT<double> LA;
   TeamLdsT<Dd> LD;
   LA.bind2(lds_raw, vb, plane, N);
-  LB.bind2(lds_raw + mat, vb, plane, N);
-  LD.bind2((Dd*)lds_raw, (Dd*)vb, plane, N);
+  LD.bind2(nullptr, vbd, plane, N);
   if ((int64_t)blockIdx.x >= a.n) return;
   const int64_t cell = a.order[blockIdx.x];
   const double P = a.P[cell];
-  const int64_t off = a.ck_off[cell];
-  const int64_t cnt = a.ck_off[cell + 1] - off - 1;
+  const int64_t cnt = a.ck_count[cell];
 
   // ---- output conversion adjoint: L = gT T + sum_k gY_k Y_k,
   //      Y_i = a_i / m, a_k = n_k W_k, a_b = n_b W_b, n_b = P V/(R T) - sum n_k
   double lam;
   {
-    const double* fin = a.ck_data + (off + cnt) * (int64_t)(N + 1);
+    const double* fin = a.ck_final + cell * (int64_t)(N + 1);
     const double phi = (lane < N) ? fin[lane] : 0.0;
     const double T = bcast(phi, 0), V = bcast(phi, 1);
     const double nk = gather(phi, lane + 2 < 64 ? lane + 2 : 0);
@@ -760,8 +810,10 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
   for (int j = lane; j < M.Nr; j += 64) pbar[j] = 0.0;
   wsync();
 
+  int64_t chunk = a.ck_head[cell];
   for (int64_t s = cnt - 1; s >= 0; --s) {
-    const double* rec = a.ck_data + (off + s) * (int64_t)(N + 1);
+    if (s % CK_CHUNK == CK_CHUNK - 1 && s != cnt - 1) chunk = a.ck_prev[chunk];   // into the previous chunk
+    const double* rec = a.ck_arena + (chunk * CK_CHUNK + s % CK_CHUNK) * (int64_t)(N + 1);
     const double x = (lane < N) ? rec[lane] : 0.0;
     const double h = rec[N];
     // ---- recompute the forward step
@@ -797,33 +849,25 @@ __global__ void __launch_bounds__(64) adjoint_team_kernel(AdjParams a) {
     F3b += mu3;
     ub1 += ROS4_C31 * ih * mu3;
     ub2 += ROS4_C32 * ih * mu3;
-    team_rhs_jac<double>(M, P, y3, LB, a.lnA);
-    const double y3b = team_jt_mu<NMAX>(LB.J, ldj, N, F3b);
-    team_pbar<double>(M, P, y3, F3b, LB, a.lnA, pbar, true);
+    const double y3b = team_vjp<double>(M, P, y3, F3b, LA, a.lnA, pbar, true);
     phib += y3b;
     ub1 += ROS4_A31 * y3b;
     ub2 += ROS4_A32 * y3b;
     const double mu2 = team_solve_t<NMAX>(F, ldj, N, invperm, rdiag, ub2);
     ub1 += ROS4_C21 * ih * mu2;
-    team_rhs_jac<double>(M, P, y2, LB, a.lnA);
-    const double y2b = team_jt_mu<NMAX>(LB.J, ldj, N, mu2);
-    team_pbar<double>(M, P, y2, mu2, LB, a.lnA, pbar, true);
+    const double y2b = team_vjp<double>(M, P, y2, mu2, LA, a.lnA, pbar, true);
     phib += y2b;
     ub1 += ROS4_A21 * y2b;
     const double mu1 = team_solve_t<NMAX>(F, ldj, N, invperm, rdiag, ub1);
     wsync();
-    // ---- J(Phi)^T mu1 and the terms through M(Phi): dual evaluations along u_i
+    // ---- J(Phi)^T mu1 and the terms through M(Phi): dual products along u_i
 #pragma unroll 1
     for (int i = 0; i < 4; ++i) {
       const double ui = (i == 0) ? u1 : (i == 1) ? u2 : (i == 2) ? u3 : u4;
       const double mui = (i == 0) ? mu1 : (i == 1) ? mu2 : (i == 2) ? mu3 : mu4;
-      team_rhs_jac<Dd>(M, P, Dd{x, (lane < N) ? ui : 0.0}, LD, a.lnA);
-      double vpart, dpart;
-      team_jt_mu_dual<NMAX>(LD.J, ldj, N, mui, vpart, dpart);
-      phib += dpart;
-      if (i == 0) phib += vpart;
-      team_pbar<Dd>(M, P, Dd{x, (lane < N) ? ui : 0.0}, mui, LD, a.lnA, pbar, i == 0);
-      wsync();
+      const Dd r = team_vjp<Dd>(M, P, Dd{x, (lane < N) ? ui : 0.0}, mui, LD, a.lnA, pbar, i == 0);
+      phib += r.d;
+      if (i == 0) phib += r.v;
     }
     lam = (lane < N) ? phib : 0.0;
   }
@@ -994,6 +1038,7 @@ struct chem_mech_s {
   std::map<hipStream_t, Workspace> ws;
   std::map<int, chem_opts> tuned;   // batch-size bucket -> autotuned options
   bool cache_read = false;
+  double ck_per_cell = 48.0;        // records per cell of the last checkpointed call (arena sizing)
 };
 
 struct chem_graph_s {
@@ -1008,15 +1053,22 @@ struct chem_ckpt_s {
   int32_t method = CHEM_METHOD_ROS4;
   hipStream_t stream = nullptr;
   int64_t n = 0;
-  double* data = nullptr;        // per cell: (Phi_n, h_n) of every accepted step, then the final Phi
-  int64_t* off = nullptr;        // [n+1] record offsets
+  // (Phi_n, h_n) of every accepted step in chunks of CK_CHUNK records, each
+  // cell's chunks linked backwards from head; the final Phi per cell
+  double* arena = nullptr;       // [cap][CK_CHUNK][N+1]
+  int64_t* prev = nullptr;       // [cap]
+  unsigned long long* used = nullptr;
+  int64_t cap = 0;
+  int64_t* head = nullptr;       // [n]
+  double* final_phi = nullptr;   // [n][N+1]
+  int32_t* count = nullptr;      // [n] accepted steps
+  std::vector<int32_t> count_host;
   double* P = nullptr;           // copy of the pressures [n]
   double* T0 = nullptr;          // copy of the initial state: T [n], Y [K][n]
   double* Y0 = nullptr;
   double* lnA = nullptr;         // [Nr] copy of the ln A override, or null
   int64_t total = 0;             // records
   int32_t* order = nullptr;      // [n] cells by decreasing record count (adjoint dispatch order)
-  std::vector<int64_t> off_host;
   std::vector<int32_t> order_host;
 };
 
@@ -1292,8 +1344,8 @@ int chem_eval(chem_mech_t m, int64_t n, const double* phi, int64_t ld, const dou
 static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const double* P,
                           const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
                           double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
-                          const double* lnA, const chem_opts* opts, double* ck_data,
-                          const int64_t* ck_off, int32_t* ck_count, hipStream_t stream);
+                          const double* lnA, const chem_opts* opts, const chem_ckpt_s* ck,
+                          hipStream_t stream);
 
 // The options a call runs with: the caller's (or the defaults), with the
 // autotuner's choice for this batch size in place of CHEM_MODE_AUTO.
@@ -1313,38 +1365,47 @@ static int resolve_opts(chem_mech_t m, int64_t n, const chem_opts* opts, chem_op
   return CHEM_OK;
 }
 
+static void set_checkpoint(IntParams& p, const chem_ckpt_s* ck) {
+  if (!ck) return;
+  p.ck_arena = ck->arena;
+  p.ck_prev = ck->prev;
+  p.ck_used = ck->used;
+  p.ck_cap = ck->cap;
+  p.ck_head = ck->head;
+  p.ck_final = ck->final_phi;
+  p.ck_count = ck->count;
+}
+
 int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P, const double* Y_in,
                    int64_t ldY, double* T_out, double* Y_out, double dt, double rtol, double atol,
                    double* h_io, int32_t* n_steps, int32_t* status, const double* lnA,
                    const chem_opts* opts, chem_ckpt_t* ckpt_out, hipStream_t stream) {
   if (!ckpt_out)
     return integrate_impl(m, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
-                          status, lnA, opts, nullptr, nullptr, nullptr, stream);
+                          status, lnA, opts, nullptr, stream);
   *ckpt_out = nullptr;
   if (!m || n <= 0 || !T_in || !P || !Y_in || !T_out || !Y_out || ldY < n) return CHEM_EINVAL;
   HIPCHECK(hipSetDevice(m->device));
   const int K = m->view.K, N = m->view.N;
-  // pass 1 counts the accepted steps of every cell (into scratch outputs, so
-  // that in-place calls keep their inputs); the integration is deterministic,
-  // so pass 2 repeats the same steps and records them
-  double *tT = nullptr, *tY = nullptr, *th = nullptr;
-  int32_t* tn = nullptr;
+  // One pass records every accepted step into an arena sized from the last
+  // checkpointed call.  If it fills up, the counts of that pass give the exact
+  // size and the call runs once more from the saved inputs (the integration is
+  // deterministic, so it repeats the same steps).
+  double* h0 = nullptr;   // the caller's initial h (or 0)
   chem_ckpt_t c = new (std::nothrow) chem_ckpt_s();
   if (!c) return CHEM_ENOMEM;
   c->mech = m;
   c->stream = stream;
   c->n = n;
   auto fail = [&](int rc) {
-    if (tT) (void)hipFree(tT);
-    if (tY) (void)hipFree(tY);
-    if (th) (void)hipFree(th);
-    if (tn) (void)hipFree(tn);
+    if (h0) (void)hipFree(h0);
     chem_ckpt_free(c);
     return rc;
   };
-  if (hipMalloc(&tT, n * 8) || hipMalloc(&tY, (size_t)K * n * 8) || hipMalloc(&th, n * 8) ||
-      hipMalloc(&tn, n * 4) || hipMalloc(&c->P, n * 8) || hipMalloc(&c->T0, n * 8) ||
-      hipMalloc(&c->Y0, (size_t)K * n * 8) || hipMalloc(&c->off, (n + 1) * 8))
+  if (hipMalloc(&h0, n * 8) || hipMalloc(&c->P, n * 8) || hipMalloc(&c->T0, n * 8) ||
+      hipMalloc(&c->Y0, (size_t)K * n * 8) || hipMalloc(&c->head, n * 8) ||
+      hipMalloc(&c->final_phi, (size_t)n * (N + 1) * 8) || hipMalloc(&c->count, n * 4) ||
+      hipMalloc(&c->used, 8))
     return fail(CHEM_ENOMEM);
   if (lnA) {
     if (hipMalloc(&c->lnA, (size_t)m->view.Nr * 8)) return fail(CHEM_ENOMEM);
@@ -1355,59 +1416,78 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
       hipMemcpy2DAsync(c->Y0, n * 8, Y_in, ldY * 8, n * 8, K, hipMemcpyDeviceToDevice, stream))
     return fail(CHEM_EHIP);
   if (h_io) {
-    if (hipMemcpyAsync(th, h_io, n * 8, hipMemcpyDeviceToDevice, stream)) return fail(CHEM_EHIP);
-  } else if (hipMemsetAsync(th, 0, n * 8, stream)) {
+    if (hipMemcpyAsync(h0, h_io, n * 8, hipMemcpyDeviceToDevice, stream)) return fail(CHEM_EHIP);
+  } else if (hipMemsetAsync(h0, 0, n * 8, stream)) {
     return fail(CHEM_EHIP);
   }
-  // both passes run the same resolved options (an autotuner update between
-  // them must not change the launch, which could change the rounding)
+  // every pass runs the same resolved options (an autotuner update between
+  // passes must not change the launch, which could change the rounding)
   chem_opts ro;
   int rc = resolve_opts(m, n, opts, &ro);
   if (rc) return fail(rc);
   c->method = ro.method;
-  rc = integrate_impl(m, n, c->T0, c->P, c->Y0, n, tT, tY, dt, rtol, atol, th, tn, nullptr,
-                      c->lnA, &ro, nullptr, nullptr, nullptr, stream);
-  if (rc) return fail(rc);
-  std::vector<int32_t> steps(n);
-  if (hipMemcpyAsync(steps.data(), tn, n * 4, hipMemcpyDeviceToHost, stream) ||
-      hipStreamSynchronize(stream))
-    return fail(CHEM_EHIP);
-  c->off_host.resize(n + 1);
-  c->off_host[0] = 0;
-  for (int64_t i = 0; i < n; ++i) c->off_host[i + 1] = c->off_host[i] + steps[i] + 1;
-  c->total = c->off_host[n];
-  if (hipMalloc(&c->data, (size_t)c->total * (N + 1) * 8)) return fail(CHEM_ENOMEM);
-  if (hipMemcpyAsync(c->off, c->off_host.data(), (n + 1) * 8, hipMemcpyHostToDevice, stream))
-    return fail(CHEM_EHIP);
+  double per_cell;
+  {
+    std::lock_guard<std::mutex> g(m->mu);
+    per_cell = m->ck_per_cell;
+  }
+  const size_t chunk_bytes = (size_t)CK_CHUNK * (N + 1) * 8;
+  int64_t cap = (int64_t)((double)n * (per_cell * 1.25 / CK_CHUNK + 1.0));
+  {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess)
+      cap = std::min<int64_t>(cap, (int64_t)(free_b / 4 / (chunk_bytes + 8)));
+    cap = std::max<int64_t>(cap, 1);
+  }
+  std::vector<int32_t> counts;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->prev) (void)hipFree(c->prev);
+    c->arena = nullptr;
+    c->prev = nullptr;
+    c->cap = cap;
+    if (hipMalloc(&c->arena, (size_t)cap * chunk_bytes) || hipMalloc(&c->prev, (size_t)cap * 8))
+      return fail(CHEM_ENOMEM);
+    if (hipMemsetAsync(c->used, 0, 8, stream)) return fail(CHEM_EHIP);
+    double* h = h_io ? h_io : nullptr;
+    if (h_io && pass > 0 && hipMemcpyAsync(h_io, h0, n * 8, hipMemcpyDeviceToDevice, stream))
+      return fail(CHEM_EHIP);
+    rc = integrate_impl(m, n, c->T0, c->P, c->Y0, n, T_out, Y_out, dt, rtol, atol, h, n_steps, status,
+                        c->lnA, &ro, c, stream);
+    if (rc) return fail(rc);
+    unsigned long long used = 0;
+    std::vector<int32_t> cnt(n);
+    if (hipMemcpyAsync(&used, c->used, 8, hipMemcpyDeviceToHost, stream) ||
+        hipMemcpyAsync(cnt.data(), c->count, n * 4, hipMemcpyDeviceToHost, stream) ||
+        hipStreamSynchronize(stream))
+      return fail(CHEM_EHIP);
+    if (pass > 0 && cnt != counts) return fail(CHEM_ENONDET);
+    counts.swap(cnt);
+    if (used <= (unsigned long long)cap) break;
+    if (pass > 0) return fail(CHEM_ENONDET);
+    // exact size from this pass's counts
+    cap = 0;
+    for (int64_t i = 0; i < n; ++i) cap += (counts[i] + CK_CHUNK - 1) / CK_CHUNK;
+    cap = std::max<int64_t>(cap, 1);
+  }
+  c->count_host = counts;
+  c->total = 0;
+  for (int64_t i = 0; i < n; ++i) c->total += counts[i] + 1;
+  {
+    std::lock_guard<std::mutex> g(m->mu);
+    m->ck_per_cell = std::max(4.0, (double)(c->total - n) / (double)n);
+  }
   // the adjoint's cost per cell is its record count: longest first
   c->order_host.resize(n);
   for (int64_t i = 0; i < n; ++i) c->order_host[i] = (int32_t)i;
   std::stable_sort(c->order_host.begin(), c->order_host.end(),
-                   [&](int32_t a, int32_t b) { return steps[a] > steps[b]; });
+                   [&](int32_t a, int32_t b) { return counts[a] > counts[b]; });
   if (hipMalloc(&c->order, n * 4)) return fail(CHEM_ENOMEM);
-  if (hipMemcpyAsync(c->order, c->order_host.data(), n * 4, hipMemcpyHostToDevice, stream))
-    return fail(CHEM_EHIP);
-  // pass 2: same inputs (the copies), the caller's outputs and h
-  double* h2 = th;
-  if (h_io) {
-    // restore the caller's initial h (pass 1 overwrote the scratch copy only)
-    h2 = h_io;
-  } else if (hipMemsetAsync(th, 0, n * 8, stream)) {
-    return fail(CHEM_EHIP);
-  }
-  rc = integrate_impl(m, n, c->T0, c->P, c->Y0, n, T_out, Y_out, dt, rtol, atol, h2, n_steps, status,
-                      c->lnA, &ro, c->data, c->off, tn, stream);
-  if (rc) return fail(rc);
-  // pass 2 must have taken exactly the steps pass 1 counted
-  std::vector<int32_t> steps2(n);
-  if (hipMemcpyAsync(steps2.data(), tn, n * 4, hipMemcpyDeviceToHost, stream) ||
+  if (hipMemcpyAsync(c->order, c->order_host.data(), n * 4, hipMemcpyHostToDevice, stream) ||
       hipStreamSynchronize(stream))
     return fail(CHEM_EHIP);
-  if (steps2 != steps) return fail(CHEM_ENONDET);
-  (void)hipFree(tT);
-  (void)hipFree(tY);
-  (void)hipFree(th);
-  (void)hipFree(tn);
+  (void)hipFree(h0);
+  h0 = nullptr;
   *ckpt_out = c;
   return CHEM_OK;
 }
@@ -1568,8 +1648,8 @@ static int team_launch(chem_mech_t m, const chem_opts& o, IntParams p, bool pers
 static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const double* P,
                           const double* Y_in, int64_t ldY, double* T_out, double* Y_out, double dt,
                           double rtol, double atol, double* h_io, int32_t* n_steps, int32_t* status,
-                          const double* lnA, const chem_opts* opts, double* ck_data,
-                          const int64_t* ck_off, int32_t* ck_count, hipStream_t stream) {
+                          const double* lnA, const chem_opts* opts, const chem_ckpt_s* ck,
+                          hipStream_t stream) {
 
   if (!m || n < 0 || n > INT32_MAX) return CHEM_EINVAL;
   if (n > 0 && (!T_in || !P || !Y_in || !T_out || !Y_out)) return CHEM_EINVAL;
@@ -1606,9 +1686,7 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
     IntParams p = make_params(m, o, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
                               status, lnA);
     p.order = order;
-    p.ck_data = ck_data;
-    p.ck_off = ck_off;
-    p.ck_count = ck_count;
+    set_checkpoint(p, ck);
     return team_launch(m, o, p, persistent, w->queue, w, stream);
   }
   const int wg = o.wg_size ? o.wg_size : 64;
@@ -1637,9 +1715,7 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
   p.ld = slots;
   p.queue = w->queue;
   p.stats = o.stats;
-  p.ck_data = ck_data;
-  p.ck_off = ck_off;
-  p.ck_count = ck_count;
+  set_checkpoint(p, ck);
   const unsigned grid = (unsigned)(slots / wg);
   if (persistent) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, w->queue);
@@ -1658,7 +1734,7 @@ int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, co
   const int N = m->view.N, Nr = m->view.Nr;
   const int64_t n = ckpt->n;
   if (N > 64 || ckpt->method != CHEM_METHOD_ROS4) return CHEM_EUNSUPPORTED;
-  const size_t lds = (2 * (size_t)N * (N + 1) + 2 * TeamLdsT<double>::vec_elems(N) + 32 + Nr) * 8;
+  const size_t lds = ((size_t)N * (N + 1) + 3 * TeamLdsT<double>::vec_elems(N) + 32 + Nr) * 8;
   HIPCHECK(hipSetDevice(m->device));
   int lds_max = 0;
   HIPCHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device));
@@ -1668,8 +1744,11 @@ int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, co
   AdjParams a;
   a.M = m->view;
   a.n = n;
-  a.ck_data = ckpt->data;
-  a.ck_off = ckpt->off;
+  a.ck_arena = ckpt->arena;
+  a.ck_prev = ckpt->prev;
+  a.ck_head = ckpt->head;
+  a.ck_final = ckpt->final_phi;
+  a.ck_count = ckpt->count;
   a.order = ckpt->order;
   a.P = ckpt->P;
   a.T0 = ckpt->T0;
@@ -1704,13 +1783,43 @@ int chem_integrate_adjoint(chem_mech_t m, chem_ckpt_t ckpt, const double* gT, co
 
 int chem_ckpt_export(chem_ckpt_t c, int64_t* off, double* records) {
   if (!c) return CHEM_EINVAL;
-  if (off)
-    for (int64_t i = 0; i <= c->n; ++i) off[i] = c->off_host[i];
+  const int64_t n = c->n;
+  if (off) {
+    off[0] = 0;
+    for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + c->count_host[i] + 1;
+  }
   if (records) {
+    // walk each cell's chunks back from its head, then lay the records out
+    // cell by cell (accepted steps in order, the final state last)
     const int N = c->mech->view.N;
+    const size_t rl = (size_t)N + 1;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return CHEM_EHIP;
-    if (hipMemcpy(records, c->data, (size_t)c->total * (N + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    std::vector<int64_t> head(n), prev(c->cap);
+    std::vector<double> arena((size_t)c->cap * CK_CHUNK * rl), fin((size_t)n * rl);
+    if (hipMemcpy(head.data(), c->head, n * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(prev.data(), c->prev, c->cap * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(arena.data(), c->arena, arena.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(fin.data(), c->final_phi, fin.size() * 8, hipMemcpyDeviceToHost) != hipSuccess)
       return CHEM_EHIP;
+    double* out = records;
+    std::vector<int64_t> chunks;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t cnt = c->count_host[i];
+      chunks.assign((size_t)((cnt + CK_CHUNK - 1) / CK_CHUNK), -1);
+      int64_t ch = head[i];
+      for (int64_t k = (int64_t)chunks.size() - 1; k >= 0; --k) {
+        if (ch < 0 || ch >= c->cap) return CHEM_EINVAL;
+        chunks[(size_t)k] = ch;
+        ch = prev[(size_t)ch];
+      }
+      for (int64_t s = 0; s < cnt; ++s) {
+        const double* r = &arena[((size_t)chunks[(size_t)(s / CK_CHUNK)] * CK_CHUNK + s % CK_CHUNK) * rl];
+        std::copy(r, r + rl, out);
+        out += rl;
+      }
+      std::copy(&fin[(size_t)i * rl], &fin[(size_t)i * rl] + rl, out);
+      out += rl;
+    }
   }
   return CHEM_OK;
 }
@@ -1778,7 +1887,7 @@ int chem_autotune(chem_mech_t m, int64_t n, const double* T_in, const double* P,
     for (int rep = 0; rep < 3 && rc == CHEM_OK; ++rep) {
       (void)hipEventRecord(e0, stream);
       rc = integrate_impl(m, ns, Ts, Ps, Ys, ns, To, Yo, dt, rtol, atol, nullptr, nullptr, nullptr,
-                          nullptr, &cand[i], nullptr, nullptr, nullptr, stream);
+                          nullptr, &cand[i], nullptr, stream);
       (void)hipEventRecord(e1, stream);
       float t = 0;
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess)
@@ -1833,7 +1942,7 @@ int chem_graph_create(chem_mech_t m, int64_t n, const double* T_in, const double
     return CHEM_EHIP;
   }
   const int rc = integrate_impl(m, n, T_in, P, Y_in, ldY, T_out, Y_out, dt, rtol, atol, h_io, n_steps,
-                                status, lnA, opts, nullptr, nullptr, nullptr, g->stream);
+                                status, lnA, opts, nullptr, g->stream);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(g->stream, &graph);
   if (rc || e != hipSuccess || !graph) {
@@ -1870,8 +1979,12 @@ void chem_graph_free(chem_graph_t g) {
 void chem_ckpt_free(chem_ckpt_t c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
-  if (c->data) (void)hipFree(c->data);
-  if (c->off) (void)hipFree(c->off);
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->prev) (void)hipFree(c->prev);
+  if (c->used) (void)hipFree(c->used);
+  if (c->head) (void)hipFree(c->head);
+  if (c->final_phi) (void)hipFree(c->final_phi);
+  if (c->count) (void)hipFree(c->count);
   if (c->P) (void)hipFree(c->P);
   if (c->T0) (void)hipFree(c->T0);
   if (c->Y0) (void)hipFree(c->Y0);

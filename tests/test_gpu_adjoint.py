@@ -1,6 +1,6 @@
 """Discrete adjoint on the GPU against the oracle's exact tangent (replayed
-along the GPU's own accepted steps) and central finite differences on frozen
-steps (h = 1e-6 in ln A).
+along the GPU's own accepted steps) and extrapolated central differences on
+frozen steps.
 
 Workload: the CH4-shaped mechanism, cells drawn like the 16,384-cell
 differentiation case (mixing-layer states, seed 205), dt = 1e-5 s; losses
@@ -230,6 +230,42 @@ def test_checkpointed_call_matches_plain_call(chem, ch4, case):
     torch.cuda.synchronize()
     assert np.array_equal(T1.cpu().numpy(), case["T1"])
     assert np.array_equal(Y1.cpu().numpy(), case["Y1"])
+    mech.close()
+
+
+def test_checkpoint_arena_refill_and_reuse(chem, small):
+    """The record arena is sized from the handle's previous checkpointed call.
+    On a fresh handle the small mechanism's cells (hundreds of accepted steps
+    each) overflow the first estimate, and the call runs once more with the
+    exact size; a second call on the same handle fits in one pass.  Both give
+    the plain call's results, one record per accepted step plus the final
+    state, and identical records."""
+    path, m, o = small
+    say("case: checkpoint arena refill, small mechanism, 256 cells, dt=1e-6")
+    T, P, Y = synth.states_small(m)
+    mech = chem.Mechanism(path)
+    T0, Y0, h0, ns0, st0 = chem.integrate(mech, dev(T), dev(P), dev(Y), 1e-6)
+    exports = []
+    for call in range(2):
+        T1, Y1, h1, ns, st, ck = chem.integrate(mech, dev(T), dev(P), dev(Y), 1e-6, checkpoint=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(T1.cpu().numpy(), T0.cpu().numpy()), call
+        assert np.array_equal(Y1.cpu().numpy(), Y0.cpu().numpy()), call
+        assert np.array_equal(ns.cpu().numpy(), ns0.cpu().numpy()), call
+        off, rec = ck.export()
+        nsn = ns.cpu().numpy()
+        assert np.array_equal(np.diff(off), nsn + 1), call
+        assert nsn.mean() > 100   # well past the first estimate of the arena
+        # each record's h is the step taken; the steps of a cell add up to dt
+        for c in range(T.size):
+            hs = rec[off[c]:off[c + 1] - 1, -1]
+            assert hs.sum() == pytest.approx(1e-6, rel=1e-12), (call, c)
+            assert rec[off[c + 1] - 1, -1] == 0.0
+            assert rec[off[c], 0] == T[c]
+        exports.append((off, rec))
+        ck.close()
+    assert np.array_equal(exports[0][0], exports[1][0])
+    assert np.array_equal(exports[0][1], exports[1][1])
     mech.close()
 
 
