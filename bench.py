@@ -84,13 +84,15 @@ def timed(c, fn, reps=1):
     return (time.perf_counter() - t) / reps
 
 
-def run_stats(c, mech, m, Tt, Pt, Yt, dt, **kw):
-    """One call with step counters: (attempts, accepted, rejected, n_steps, status)."""
-    stats = c.torch.zeros(3, dtype=c.torch.int64, device=c.dev)
+def run_stats(c, mech, m, Tt, Pt, Yt, dt, with_jac=False, **kw):
+    """One call with step counters: (attempts, accepted, rejected, n_steps,
+    status), and the Jacobian evaluations last when with_jac is set."""
+    stats = c.torch.zeros(4, dtype=c.torch.int64, device=c.dev)
     r = c.chem.integrate(mech, Tt, Pt, Yt, dt, opts=c.chem.default_opts(stats=stats, **kw))
     c.sync()
-    a, acc, rej = (int(x) for x in stats.cpu().numpy())
-    return a, acc, rej, r[3].cpu().numpy(), r[4].cpu().numpy()
+    a, acc, rej, je = (int(x) for x in stats.cpu().numpy())
+    out = (a, acc, rej, r[3].cpu().numpy(), r[4].cpu().numpy())
+    return out + (je,) if with_jac else out
 
 
 def headline(c, a):
@@ -202,7 +204,8 @@ def mixing(c, a):
 
 def methods(c, a):
     """Cells/s of each solver and of the filtered estimate on the mixing case
-    (default launch), with their step counts."""
+    (default launch), with their step counts; the W-method ROS34PW2 also with
+    the Jacobian kept for 2, 4 and 8 accepted steps."""
     chem, synth = c.chem, c.synth
     path, m = synth.mechanism_file("ch4", c.mech_dir)
     T, P, Y = synth.states_mixing(m, 65536, 202)
@@ -210,13 +213,17 @@ def methods(c, a):
     mech = chem.Mechanism(path, device=0)
     Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
     out = {}
-    for meth in ("ros4", "ros3", "rodas3", "rodas4"):
-        for est in ("embedded", "filtered"):
-            o = chem.default_opts(method=meth, estimator=est)
-            chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o)
-            t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o), 2)
-            att, acc, rej, _, _ = run_stats(c, mech, m, Tt, Pt, Yt, 1e-6, method=meth, estimator=est)
-            out["%s_%s" % (meth, est)] = {"cells_per_s": round(n / t, 1), "accepted": acc, "rejected": rej}
+    cases = [(meth, est, 1) for meth in ("ros4", "ros3", "rodas3", "rodas4", "ros34pw2")
+             for est in ("embedded", "filtered")]
+    cases += [("ros34pw2", "embedded", k) for k in (2, 4, 8)]
+    for meth, est, k in cases:
+        o = chem.default_opts(method=meth, estimator=est, jac_every=k)
+        chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o)
+        t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, opts=o), 2)
+        att, acc, rej, _, _, je = run_stats(c, mech, m, Tt, Pt, Yt, 1e-6, with_jac=True, method=meth,
+                                            estimator=est, jac_every=k)
+        key = "%s_%s" % (meth, est) + ("_jac%d" % k if k > 1 else "")
+        out[key] = {"cells_per_s": round(n / t, 1), "accepted": acc, "rejected": rej, "jacobians": je}
     mech.close()
     return out
 
@@ -340,20 +347,23 @@ def work_precision(c, a):
     ref_ok = np.concatenate(ref_status) == 0
     Tt, Pt, Yt = c.d(T), c.d(P), c.d(Y)
     pts = []
-    for meth in ("ros3", "ros4", "rodas3", "rodas4"):
-        for est in ("embedded", "filtered"):
-            for e in range(4, 13):
-                tol = 10.0 ** -e
-                o = chem.default_opts(method=meth, estimator=est)
-                r = chem.integrate(mech, Tt, Pt, Yt, 1e-6, rtol=tol, atol=tol, opts=o)
-                t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, rtol=tol, atol=tol, opts=o))
-                y = np.vstack([r[0].cpu().numpy(), r[1].cpu().numpy()])
-                ok = ref_ok & (r[4].cpu().numpy() == 0)
-                E = np.sqrt((((yref - y) / (1e-10 + 1e-6 * np.abs(yref))) ** 2).sum(0))[ok]
-                pts.append({"method": meth, "estimator": est, "tol": tol, "error_norm": float(E.max()) if E.size else None,
-                            "error_norm_median": float(np.median(E)) if E.size else None, "ms": round(t * 1e3, 3),
-                            "failed": int((r[4] != 0).sum().item())})
-            log("work-precision: %s %s done" % (meth, est))
+    cases = [(meth, est, 1) for meth in ("ros3", "ros4", "rodas3", "rodas4", "ros34pw2")
+             for est in ("embedded", "filtered")]
+    cases += [("ros34pw2", "embedded", 4)]
+    for meth, est, k in cases:
+        for e in range(4, 13):
+            tol = 10.0 ** -e
+            o = chem.default_opts(method=meth, estimator=est, jac_every=k)
+            r = chem.integrate(mech, Tt, Pt, Yt, 1e-6, rtol=tol, atol=tol, opts=o)
+            t = timed(c, lambda: chem.integrate(mech, Tt, Pt, Yt, 1e-6, rtol=tol, atol=tol, opts=o))
+            y = np.vstack([r[0].cpu().numpy(), r[1].cpu().numpy()])
+            ok = ref_ok & (r[4].cpu().numpy() == 0)
+            E = np.sqrt((((yref - y) / (1e-10 + 1e-6 * np.abs(yref))) ** 2).sum(0))[ok]
+            pts.append({"method": meth, "estimator": est, "jac_every": k, "tol": tol,
+                        "error_norm": float(E.max()) if E.size else None,
+                        "error_norm_median": float(np.median(E)) if E.size else None, "ms": round(t * 1e3, 3),
+                        "failed": int((r[4] != 0).sum().item())})
+        log("work-precision: %s %s jac_every=%d done" % (meth, est, k))
     mech.close()
     return {"workload": "%d of the 65,536 CH4 mixing-layer cells (64 with the most steps), dt=1e-6 s" % idx.size,
             "reference": "oracle RODAS4, rtol 1e-14, atol 1e-18, %.1f s on %d threads; %d of %d cells "

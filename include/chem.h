@@ -80,6 +80,9 @@ extern "C" {
 #define CHEM_METHOD_ROS3 1      /* 3 stages, order 3(2), Sandu et al. */
 #define CHEM_METHOD_RODAS3 2    /* 4 stages, order 3(2), stiffly accurate, Sandu et al. */
 #define CHEM_METHOD_RODAS4 3    /* 6 stages, order 4(3), stiffly accurate, Hairer-Wanner */
+#define CHEM_METHOD_ROS34PW2 4  /* 4 stages, order 3(2), stiffly accurate W-method (Rang and
+                                   Angermann 2005): keeps its order with a Jacobian kept over
+                                   several steps (chem_opts.jac_every), the paper's future work */
 
 /* ---- error estimate (chem_opts.estimator) ------------------------------ */
 #define CHEM_EST_EMBEDDED 0     /* the method's own: difference of the two solutions */
@@ -112,8 +115,13 @@ typedef struct {
   int32_t team_waves;     /* team modes: wavefronts per cell, 0 = library choice: 1 for
                              N <= 64, 4 for 64 < N <= 128 (the only sizes each is built for:
                              another value is CHEM_EUNSUPPORTED; not 0, 1 or 4: CHEM_EINVAL) */
-  unsigned long long* stats; /* nullable DEVICE pointer to 3 counters that the call adds to:
-                                attempted steps, accepted steps, rejected steps (all cells) */
+  int32_t jac_every;      /* J is evaluated at every jac_every-th accepted state of a cell and
+                             kept in between (1: every step; only a W-method keeps its order
+                             with a kept J).  > 1 is CHEM_EUNSUPPORTED with four wavefronts per
+                             cell on a plain grid or without allocation, and for checkpoints */
+  unsigned long long* stats; /* nullable DEVICE pointer to 4 counters that the call adds to:
+                                attempted steps, accepted steps, rejected steps, Jacobian
+                                evaluations (all cells) */
 } chem_opts;
 
 /* Defaults listed above. */

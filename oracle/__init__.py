@@ -72,17 +72,18 @@ def lib(path=None):
         L.or_integrate.restype = C.c_int
         L.or_integrate.argtypes = [C.c_void_p, C.c_int64, _d, _d, _d, C.c_int64, C.c_double, C.c_double,
                                    C.c_double, _d, _d, _d, _i, _i, _i, _d, C.c_int, C.c_int, C.c_int,
-                                   C.c_int]
+                                   C.c_int, C.c_int]
         L.or_record_steps.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, C.c_double, C.c_double,
-                                      C.c_double, C.c_double, _d, _d, C.c_int, _d, _d, C.c_int, C.c_int]
+                                      C.c_double, C.c_double, _d, _d, C.c_int, _d, _d, C.c_int, C.c_int,
+                                      C.c_int]
         L.or_replay.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d, _d, C.c_int, _d, _d, C.c_int]
         L.or_tangent.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d, _d, C.c_int, _d,
                                  C.c_double, _d, _d, _d, C.c_int]
         L.or_integrate_linear.argtypes = [C.c_int, _d, _d, C.c_double, C.c_double, C.c_double, C.c_double,
                                           C.c_int, C.c_int]
-        L.or_linear_step.argtypes = [C.c_int, _d, _d, C.c_double, _d, _d, C.c_int, C.c_int]
+        L.or_linear_step.argtypes = [C.c_int, _d, _d, C.c_double, _d, _d, C.c_int, C.c_int, _d]
         L.or_integrate_cubic.argtypes = [_d, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
-                                           C.c_int]
+                                           C.c_int, C.c_int]
         if path is not None:
             return L
         _lib = L
@@ -108,7 +109,7 @@ R_U = 8314.462618
 P_ATM = 101325.0
 
 # Rosenbrock solvers of the paper's solver table and the error estimators
-METHODS = {"ros4": 0, "ros3": 1, "rodas3": 2, "rodas4": 3}
+METHODS = {"ros4": 0, "ros3": 1, "rodas3": 2, "rodas4": 3, "ros34pw2": 4}
 ESTIMATORS = {"embedded": 0, "filtered": 1}
 
 
@@ -186,8 +187,10 @@ class Oracle:
 
     # -- batched integration ---------------------------------------------------
     def integrate(self, T, P, Y, dt, rtol=1e-6, atol=1e-10, h=None, lnA=None, max_steps=0,
-                  nthreads=0, method="ros4", estimator="embedded"):
-        """Y is (K, n).  Returns dict with T, Y, h, n_acc, n_rej, status, threads."""
+                  nthreads=0, method="ros4", estimator="embedded", jac_every=1):
+        """Y is (K, n).  Returns dict with T, Y, h, n_acc, n_rej, status, threads.
+        jac_every: J evaluated at every jac_every-th accepted state and kept
+        in between (a W-method keeps its order with such a J)."""
         T = _f64(T)
         P = _f64(P)
         Y = _f64(Y)
@@ -199,19 +202,19 @@ class Oracle:
         na, nr, st = (np.zeros(n, np.int32) for _ in range(3))
         thr = self.L.or_integrate(self.h, n, _p(T), _p(P), _p(Y), n, float(dt), float(rtol), float(atol),
                                   _p(hio), _p(Tout), _p(Yout), _p(na), _p(nr), _p(st), _p(_f64(lnA)),
-                                  int(max_steps), int(nthreads), _mid(method), _eid(estimator))
+                                  int(max_steps), int(nthreads), _mid(method), _eid(estimator), int(jac_every))
         if thr < 0:
             raise ValueError("unknown method")
         return dict(T=Tout, Y=Yout, h=hio, n_acc=na, n_rej=nr, status=st, threads=thr)
 
     def record_steps(self, T, P, Y, dt, rtol=1e-6, atol=1e-10, h0=0.0, lnA=None, cap=1000000,
-                     method="ros4", estimator="embedded"):
+                     method="ros4", estimator="embedded", jac_every=1):
         hs = np.zeros(cap)
         To = np.zeros(1)
         Yo = np.zeros(self.K)
         n = self.L.or_record_steps(self.h, float(T), float(P), _p(_f64(Y)), float(dt), float(rtol),
                                    float(atol), float(h0), _p(_f64(lnA)), _p(hs), cap, _p(To), _p(Yo),
-                                   _mid(method), _eid(estimator))
+                                   _mid(method), _eid(estimator), int(jac_every))
         if n < 0:
             raise RuntimeError("oracle integration failed with status %d" % -n)
         return hs[:n].copy(), To[0], Yo
@@ -264,20 +267,24 @@ def integrate_linear(A, y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0, method="ros4
     return y, n
 
 
-def linear_step(A, y0, h, method="ros4", estimator="embedded"):
-    """One step of y' = A y: (y_new, error estimate)."""
+def linear_step(A, y0, h, method="ros4", estimator="embedded", Ajac=None):
+    """One step of y' = A y: (y_new, error estimate).  Ajac (optional) stands
+    in for the Jacobian A."""
     A = _f64(A)
     y = _f64(y0)
     out, err = np.zeros_like(y), np.zeros_like(y)
-    rc = lib().or_linear_step(y.size, _p(A), _p(y), float(h), _p(out), _p(err), _mid(method), _eid(estimator))
+    rc = lib().or_linear_step(y.size, _p(A), _p(y), float(h), _p(out), _p(err), _mid(method), _eid(estimator),
+                              _p(_f64(Ajac)))
     if rc:
         raise np.linalg.LinAlgError("step failed")
     return out, err
 
 
-def integrate_cubic(y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0, method="ros4", estimator="embedded"):
-    """y' = -y^3 from y0 over [0, dt]."""
+def integrate_cubic(y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0, method="ros4", estimator="embedded",
+                    jac_every=1):
+    """y' = -y^3 from y0 over [0, dt]; jac_every > 1 keeps the Jacobian of
+    every jac_every-th step's state in between."""
     y = np.array([float(y0)])
     n = lib().or_integrate_cubic(_p(y), float(dt), float(rtol), float(atol), float(h_fixed), _mid(method),
-                                   _eid(estimator))
+                                   _eid(estimator), int(jac_every))
     return y[0], n

@@ -1,5 +1,6 @@
 // CPU FP64 oracle for batched constant-pressure chemistry integration with the
-// linearly implicit Rosenbrock solvers ROS4 (the default), ROS3, RODAS3, RODAS4.
+// linearly implicit Rosenbrock solvers ROS4 (the default), ROS3, RODAS3, RODAS4,
+// and the W-method ROS34PW2 with the Jacobian kept over several steps.
 //
 // TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
 // includes this file; only the tests, the smoke check and the CPU-baseline leg
@@ -378,12 +379,74 @@ const Method RODAS4 = {
     {0.0, 0.0, 0.0, 0.0, 0.0, 1.0},
     4.0};
 
+// The transformed coefficients from a method's standard form (alpha_ij,
+// gamma_ij with gamma_ii = gamma, weights b and embedded weights bhat):
+// a = alpha Gamma^-1, C = diag(1/gamma) - Gamma^-1, m = b Gamma^-1,
+// e = (b - bhat) Gamma^-1, Gamma^-1 by forward substitution.
+Method transformed(const char* name, int s, double gamma, const double al[6][6], const double ga[6][6],
+                   const double* b, const double* bh, double elo) {
+  double G[6][6] = {{0}}, Gi[6][6] = {{0}};
+  for (int i = 0; i < s; ++i) {
+    for (int j = 0; j < i; ++j) G[i][j] = ga[i][j];
+    G[i][i] = gamma;
+  }
+  for (int c = 0; c < s; ++c)        // column c of Gamma^-1: Gamma x = e_c
+    for (int i = 0; i < s; ++i) {
+      double r = (i == c) ? 1.0 : 0.0;
+      for (int j = 0; j < i; ++j) r -= G[i][j] * Gi[j][c];
+      Gi[i][c] = r / G[i][i];
+    }
+  Method mt = {name, s, gamma, {{0}}, {{0}}, {0}, {0}, elo};
+  for (int i = 0; i < s; ++i) {
+    for (int j = 0; j < i; ++j) {
+      double a = 0;
+      for (int l = 0; l < s; ++l) a += al[i][l] * Gi[l][j];
+      mt.a[i][j] = a;
+      mt.c[i][j] = -Gi[i][j];
+    }
+  }
+  for (int j = 0; j < s; ++j) {
+    double m = 0, e = 0;
+    for (int l = 0; l < s; ++l) {
+      m += b[l] * Gi[l][j];
+      e += (b[l] - bh[l]) * Gi[l][j];
+    }
+    mt.m[j] = m;
+    mt.e[j] = e;
+  }
+  return mt;
+}
+
+// ROS34PW2 of Rang and Angermann (2005): a W-method - its order conditions
+// hold for any matrix in the place of J, so a Jacobian kept from an earlier
+// step leaves it of order 3 (embedded 2); stiffly accurate.  Published in the
+// standard form.
+Method make_ros34pw2() {
+  const double g = 0.435866521508459;
+  double al[6][6] = {{0}}, ga[6][6] = {{0}};
+  al[1][0] = 0.87173304301691801;
+  al[2][0] = 0.84457060015369423;
+  al[2][1] = -0.11299064236484185;
+  al[3][2] = 1.0;
+  ga[1][0] = -0.87173304301691801;
+  ga[2][0] = -0.90338057013044082;
+  ga[2][1] = 0.054180672388095326;
+  ga[3][0] = 0.24212380706095346;
+  ga[3][1] = -1.2232505839045147;
+  ga[3][2] = 0.54526025533510214;
+  const double b[4] = {0.24212380706095346, -1.2232505839045147, 1.5452602553351020, 0.435866521508459};
+  const double bh[4] = {0.37810903145819369, -0.096042292212423178, 0.5, 0.2179332607542295};
+  return transformed("ros34pw2", 4, g, al, ga, b, bh, 3.0);
+}
+const Method ROS34PW2 = make_ros34pw2();
+
 const Method* method_of(int id) {
   switch (id) {
     case 0: return &ROS4;
     case 1: return &ROS3;
     case 2: return &RODAS3;
     case 3: return &RODAS4;
+    case 4: return &ROS34PW2;
     default: return nullptr;
   }
 }
@@ -426,14 +489,19 @@ enum { EST_EMBEDDED = 0, EST_FILTERED = 1 };
 // One step of size h from y with method `mt`.  Returns the LU's code (0 =
 // success).  Stages whose argument equals the previous stage's (row i of a
 // equal to row i-1) share that stage's f, as the methods are built for.
+// Jac (optional) stands in for J(y): a Jacobian kept from an earlier state,
+// which only a W-method tolerates without losing its order.
 template <class Sys, class S>
 int ros_step(const Sys& sys, const Method& mt, const S* y, const S* lnA, double h, int estimator,
-             S* ynew, S* err) {
+             S* ynew, S* err, const S* Jac = nullptr) {
   const int n = sys.n(), s = mt.s;
   std::vector<S> J(n * n), Yi(n), F(n);
   std::vector<std::vector<S>> u(s, std::vector<S>(n));
   std::vector<int> piv(n);
-  sys.jac(y, lnA, J.data());
+  if (Jac)
+    for (int i = 0; i < n * n; ++i) J[i] = Jac[i];
+  else
+    sys.jac(y, lnA, J.data());
   for (int i = 0; i < n * n; ++i) J[i] = -J[i];
   for (int i = 0; i < n; ++i) J[i * n + i] += 1.0 / (h * mt.gamma);
   int rc = lu(n, J.data(), piv.data());
@@ -477,6 +545,7 @@ struct Ctl {
   int max_bad = 10;
   const Method* mt = &ROS4;
   int estimator = EST_EMBEDDED;
+  int jac_every = 1;   // J evaluated at every jac_every-th accepted state, kept in between
 };
 
 struct Outcome { int accepted = 0, rejected = 0, status = 0; double h_next = 0; };
@@ -488,19 +557,24 @@ template <class Sys>
 Outcome integrate(const Sys& sys, double* y, double dt, double h0, const Ctl& c,
                   const double* lnA, std::vector<double>* hist = nullptr) {
   const int n = sys.n();
-  std::vector<double> ynew(n), err(n);
+  std::vector<double> ynew(n), err(n), Jk(n * n);
   Outcome o;
   double h = (h0 > 0) ? h0 : dt;
   double rem = dt;
   bool last_rejected = false;
   int bad = 0;
   int attempts = 0;
+  int since_jac = c.jac_every;   // accepted steps since J was evaluated
   while (rem > 0) {
     if (attempts >= c.max_steps) { o.status = 1; break; }
     if (h < c.h_min) { o.status = 2; break; }
     ++attempts;
     double hs = std::min(h, rem);
-    int rc = ros_step(sys, *c.mt, y, lnA, hs, c.estimator, ynew.data(), err.data());
+    if (since_jac >= c.jac_every) {   // a rejected step keeps the J of its state
+      sys.jac(y, lnA, Jk.data());
+      since_jac = 0;
+    }
+    int rc = ros_step(sys, *c.mt, y, lnA, hs, c.estimator, ynew.data(), err.data(), Jk.data());
     bool ok = rc == 0;
     double e = 0;
     if (ok) {
@@ -523,6 +597,7 @@ Outcome integrate(const Sys& sys, double* y, double dt, double h0, const Ctl& c,
       for (int i = 0; i < n; ++i) y[i] = ynew[i];
       rem -= hs;
       ++o.accepted;
+      ++since_jac;
       if (hist) hist->push_back(hs);
       fac = std::min(c.fac_max, std::max(c.fac_min, fac));
       if (last_rejected) fac = std::min(fac, 1.0);
@@ -588,8 +663,10 @@ void tangent(const Mech& m, const Method& mt, double P, double T0, const double*
 }  // namespace
 
 // ============================================================== C interface
-// `method`: 0 ROS4, 1 ROS3, 2 RODAS3, 3 RODAS4; `estimator`: 0 embedded,
-// 1 filtered.  Functions taking them return -100 for an unknown method.
+// `method`: 0 ROS4, 1 ROS3, 2 RODAS3, 3 RODAS4, 4 ROS34PW2; `estimator`:
+// 0 embedded, 1 filtered; `jac_every` (>= 1): J evaluated at every
+// jac_every-th accepted state and kept in between.  Functions taking a method
+// return -100 for an unknown one.
 extern "C" {
 
 void* or_mech_load(const char* path) {
@@ -669,7 +746,7 @@ void or_from_phi(void* h, double P, const double* phi, double* T, double* Y) {
 int or_integrate(void* hm, int64_t n, const double* T, const double* P, const double* Y, int64_t ldY,
                  double dt, double rtol, double atol, double* h_io, double* T_out, double* Y_out,
                  int32_t* n_acc, int32_t* n_rej, int32_t* status, const double* lnA, int max_steps,
-                 int nthreads, int method, int estimator) {
+                 int nthreads, int method, int estimator, int jac_every) {
   const Mech& m = *(const Mech*)hm;
   const Method* mt = method_of(method);
   if (!mt) return -100;
@@ -678,6 +755,7 @@ int or_integrate(void* hm, int64_t n, const double* T, const double* P, const do
   c.rtol = rtol; c.atol = atol;
   c.mt = mt;
   c.estimator = estimator;
+  c.jac_every = jac_every > 0 ? jac_every : 1;
   if (max_steps > 0) c.max_steps = max_steps;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
   for (int64_t cell = 0; cell < n; ++cell) {
@@ -703,7 +781,7 @@ int or_integrate(void* hm, int64_t n, const double* T, const double* P, const do
 // One cell: integrate and return the accepted step sizes (capacity cap).
 int or_record_steps(void* hm, double T, double P, const double* Y, double dt, double rtol,
                     double atol, double h0, const double* lnA, double* hs, int cap, double* T_out,
-                    double* Y_out, int method, int estimator) {
+                    double* Y_out, int method, int estimator, int jac_every) {
   const Mech& m = *(const Mech*)hm;
   const Method* mt = method_of(method);
   if (!mt) return -100;
@@ -715,6 +793,7 @@ int or_record_steps(void* hm, double T, double P, const double* Y, double dt, do
   c.rtol = rtol; c.atol = atol;
   c.mt = mt;
   c.estimator = estimator;
+  c.jac_every = jac_every > 0 ? jac_every : 1;
   std::vector<double> hist;
   Outcome o = integrate(sys, phi.data(), dt, h0, c, lnA, &hist);
   from_phi(m, P, phi.data(), T_out, Y_out);
@@ -778,25 +857,30 @@ int or_integrate_linear(int n, const double* A, double* y, double dt, double rto
   return o.status ? -o.status : o.accepted;
 }
 
-// One step of y' = A y: the new state and the error estimate.
+// One step of y' = A y: the new state and the error estimate.  Ajac
+// (nullable) stands in for the Jacobian A.
 int or_linear_step(int n, const double* A, const double* y, double h, double* ynew, double* err,
-                   int method, int estimator) {
+                   int method, int estimator, const double* Ajac) {
   const Method* mt = method_of(method);
   if (!mt) return -100;
   LinSys sys{n, A};
-  return ros_step(sys, *mt, y, (const double*)nullptr, h, estimator, ynew, err) ? -1 : 0;
+  return ros_step(sys, *mt, y, (const double*)nullptr, h, estimator, ynew, err, Ajac) ? -1 : 0;
 }
 
+// y' = -y^3.  jac_every > 1: the Jacobian is evaluated at every jac_every-th
+// step's state and kept in between (as the controller's reuse does).
 int or_integrate_cubic(double* y, double dt, double rtol, double atol, double h_fixed, int method,
-                       int estimator) {
+                       int estimator, int jac_every) {
   const Method* mt = method_of(method);
   if (!mt) return -100;
   CubicSys sys;
+  if (jac_every < 1) jac_every = 1;
   if (h_fixed > 0) {
-    double ynew, err;
+    double ynew, err, Jk = 0;
     int steps = (int)std::llround(dt / h_fixed);
     for (int s = 0; s < steps; ++s) {
-      ros_step(sys, *mt, y, (const double*)nullptr, h_fixed, estimator, &ynew, &err);
+      if (s % jac_every == 0) sys.jac(y, (const double*)nullptr, &Jk);
+      ros_step(sys, *mt, y, (const double*)nullptr, h_fixed, estimator, &ynew, &err, &Jk);
       y[0] = ynew;
     }
     return steps;
@@ -805,6 +889,7 @@ int or_integrate_cubic(double* y, double dt, double rtol, double atol, double h_
   c.rtol = rtol; c.atol = atol;
   c.mt = mt;
   c.estimator = estimator;
+  c.jac_every = jac_every;
   Outcome o = integrate(sys, y, dt, 0.0, c, nullptr);
   return o.status ? -o.status : o.accepted;
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libchem.so")
 OK, EINVAL, EPARSE, EHIP, ENOMEM, EUNSUPPORTED, ENONDET = 0, -1, -2, -3, -4, -5, -6
 MODE_AUTO, MODE_PLAIN, MODE_PERSISTENT, MODE_TEAM, MODE_TEAM_PERSISTENT = 0, 1, 2, 3, 4
 MODES = {"auto": 0, "plain": 1, "persistent": 2, "team": 3, "team_persistent": 4}
-METHODS = {"ros4": 0, "ros3": 1, "rodas3": 2, "rodas4": 3}
+METHODS = {"ros4": 0, "ros3": 1, "rodas3": 2, "rodas4": 3, "ros34pw2": 4}
 ESTIMATORS = {"embedded": 0, "filtered": 1}
 CELL_OK, CELL_MAX_STEPS, CELL_H_MIN, CELL_NONFINITE, CELL_SINGULAR = 0, 1, 2, 3, 4
 
@@ -36,7 +36,7 @@ class Opts(C.Structure):
                 ("T_cut", C.c_double), ("max_steps", C.c_int32), ("mode", C.c_int32),
                 ("wg_size", C.c_int32), ("waves_per_cu", C.c_int32), ("order", C.c_int32),
                 ("method", C.c_int32), ("estimator", C.c_int32), ("team_waves", C.c_int32),
-                ("stats", C.c_void_p)]
+                ("jac_every", C.c_int32), ("stats", C.c_void_p)]
 
 
 _vp = C.c_void_p
@@ -125,8 +125,9 @@ def default_opts(**kw):
         if k == "estimator" and isinstance(v, str):
             v = ESTIMATORS[v]
         if k == "stats":
-            # a (3,) int64 device tensor that the call adds attempts/accepted/rejected to
-            v = _ptr(v, "stats", torch.int64, (3,))
+            # a (4,) int64 device tensor that the call adds attempts, accepted,
+            # rejected steps and Jacobian evaluations to
+            v = _ptr(v, "stats", torch.int64, (4,))
         setattr(o, k, v)
     return o
 

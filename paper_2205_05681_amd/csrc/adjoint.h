@@ -131,21 +131,22 @@ __device__ S team_vjp(const MechView& M, double P, S y, double mu, TeamLdsT<S>& 
   const S lnT = log(T), iT = 1.0 / T;
   S tacc = sc<S>(0.0), bacc = sc<S>(0.0);   // this lane's sums of qbar dq/dT and qbar beta
   S* const dummy = L.dwdT + lane;           // target of the updates of unused slots
-  for (int j = lane; j < M.Nr; j += 64) {
-    const RateOutT<S> r = reaction_rate(M, j, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
-                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, lnA, true);
-    const int32_t* info = M.rinfo + 8 * j;
-    const int32_t* sp = M.rspec + 6 * j;
-    const int32_t* nu = M.rnu + 6 * j;
-    const int nr = info[1], np = info[2];
+  const int Nr = M.Nr;
+  RxnRec nx = load_rxn(M, lane < Nr ? lane : Nr - 1, lnA);   // fetched one reaction ahead
+  for (int j = lane; j < Nr; j += 64) {
+    const RxnRec R = nx;
+    nx = load_rxn(M, j + 64 < Nr ? j + 64 : j, lnA);
+    const RateOutT<S> r = reaction_rate(M, R, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
+                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, true);
+    const int nr = R.nr, np = R.np;
     int ks[6], nus[6];
     bool on[6];
     S cs[6], ws[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       on[q] = (q < 3) ? (q < nr) : (q - 3 < np);
-      ks[q] = sp[q];              // unused slots hold species 0 and coefficient 0
-      nus[q] = nu[q];
+      ks[q] = R.sp[q];            // unused slots hold species 0 and coefficient 0
+      nus[q] = R.nu[q];
       cs[q] = L.conc[ks[q]];
       ws[q] = L.tb[ks[q]];
     }
@@ -181,12 +182,12 @@ __device__ S team_vjp(const MechView& M, double P, S y, double mu, TeamLdsT<S>& 
       lds_add(on[q] ? &L.gb[ks[q]] : dummy, qb * dq[q]);
     }
     tacc += qb * (r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT);
-    if (info[0] != RX_ELEM) {
+    if (R.type != RX_ELEM) {
       // [M] = sum C + sum (alpha - 1) C: the uniform part summed per lane, the
       // listed efficiencies scattered (the first four read together)
       const S qbb = qb * r.beta;
       bacc += qbb;
-      const int e0 = info[3], e1 = info[4];
+      const int e0 = R.e0, e1 = R.e1;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int e = (e0 + t < e1) ? e0 + t : e0;

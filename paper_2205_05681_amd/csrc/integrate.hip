@@ -50,6 +50,7 @@ struct IntParams {
   double dt, rtol, atol, h_min, safety, fac_min, fac_max, T_cut;
   int32_t max_steps;
   int32_t estimator;           // CHEM_EST_*
+  int32_t jac_every;           // J at every jac_every-th accepted state, kept in between
   RosTable tab;                // the method's coefficients
   double* h_io;
   int32_t* n_steps;
@@ -215,7 +216,8 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
   // per-cell controller state
   double P = 0, h = 0, rem = 0;
   int attempts = 0, accepted = 0, bad = 0, status = 0;
-  bool last_rej = false, need_jac = true, done = false;
+  bool last_rej = false, need_f = false, done = false;
+  int since_jac = 0, jac_evals = 0;   // accepted steps since J was evaluated; J evaluations
   int64_t ck_chunk = -1;
 
   auto init = [&](int64_t c) {
@@ -227,7 +229,9 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
     if (p.h_io && p.h_io[c] > 0.0) h = p.h_io[c];
     attempts = accepted = bad = status = 0;
     last_rej = false;
-    need_jac = true;
+    since_jac = p.jac_every;
+    need_f = false;
+    jac_evals = 0;
     done = !(T >= p.T_cut);     // T_cut = 0 integrates every cell (NaN T included)
     if (p.T_cut <= 0.0) done = false;
     ck_chunk = -1;
@@ -250,6 +254,7 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
       atomicAdd(&p.stats[0], (unsigned long long)attempts);
       atomicAdd(&p.stats[1], (unsigned long long)accepted);
       atomicAdd(&p.stats[2], (unsigned long long)(attempts - accepted));
+      atomicAdd(&p.stats[3], (unsigned long long)jac_evals);
     }
   };
   if (have) init(cell);
@@ -267,9 +272,16 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
     if (!done) {
       ++attempts;
       const double hs = fmin(h, rem);
-      if (need_jac) {
+      // J at every jac_every-th accepted state (and the first); in between
+      // only f at the new state - a rejected step keeps both
+      if (since_jac >= p.jac_every) {
         eval_rhs_jac(M, P, phi, f1, J, L, base, ld, p.lnA);
-        need_jac = false;
+        since_jac = 0;
+        need_f = false;
+        ++jac_evals;
+      } else if (need_f) {
+        eval_rhs(M, P, phi, f1, conc, wdot, hrt, cpr, gib, p.lnA);
+        need_f = false;
       }
       const RosTable& R = p.tab;
       const double d = 1.0 / (hs * R.gamma);
@@ -347,7 +359,8 @@ __global__ void __launch_bounds__(256) integrate_thread_kernel(IntParams p) {
           fac = fmin(p.fac_max, fmax(p.fac_min, fac));
           if (last_rej) fac = fmin(fac, 1.0);
           last_rej = false;
-          need_jac = true;
+          ++since_jac;
+          need_f = true;
           if (rem <= 0.0) done = true;
         } else {
           fac = fmin(1.0, fmax(p.fac_min, fac));
@@ -406,7 +419,8 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
     double rem = p.dt, h = p.dt;
     if (p.h_io && p.h_io[cell] > 0.0) h = p.h_io[cell];
     int attempts = 0, accepted = 0, bad = 0, status = 0;
-    bool last_rej = false, need_jac = true;   // need_jac: Phi changed since J was evaluated
+    bool last_rej = false, need_f = false;   // need_f: Phi changed since f1 was evaluated
+    int since_jac = p.jac_every, jac_evals = 0;   // accepted steps since J was evaluated
     bool done = (p.T_cut > 0.0) && !(T0 >= p.T_cut);
     int64_t ck_chunk = -1;
     double f1 = 0.0;
@@ -421,11 +435,17 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
       }
       ++attempts;
       const double hs = fmin(h, rem);
-      // J(Phi) into LDS after an accepted step; a rejected step keeps it
-      // (same Phi; the factors live in registers, J is not overwritten)
-      if (need_jac) {
+      // J(Phi) into LDS at every jac_every-th accepted state (and the first),
+      // in between only f at the new state; a rejected step keeps both (same
+      // Phi; the factors live in registers, J is not overwritten)
+      if (since_jac >= p.jac_every) {
         f1 = team_rhs_jac(M, P, phi, L, p.lnA);
-        need_jac = false;
+        since_jac = 0;
+        need_f = false;
+        ++jac_evals;
+      } else if (need_f) {
+        f1 = team_rhs(M, P, phi, L, p.lnA);
+        need_f = false;
       }
       // factors of M = I/(h gamma) - J, row i in lane i's registers
       RegLU<NMAX> F;
@@ -484,7 +504,8 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
           }
         }
         phi = ynew;
-        need_jac = true;
+        ++since_jac;
+        need_f = true;
         rem -= hs;
         ++accepted;
         fac = fmin(p.fac_max, fmax(p.fac_min, fac));
@@ -526,6 +547,7 @@ __global__ void __launch_bounds__(64) integrate_team_kernel(IntParams p, bool PE
           atomicAdd(&p.stats[0], (unsigned long long)attempts);
           atomicAdd(&p.stats[1], (unsigned long long)accepted);
           atomicAdd(&p.stats[2], (unsigned long long)(attempts - accepted));
+          atomicAdd(&p.stats[3], (unsigned long long)jac_evals);
         }
       }
     }
@@ -582,7 +604,8 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
     double rem = p.dt, h = p.dt;
     if (p.h_io && p.h_io[cell] > 0.0) h = p.h_io[cell];
     int attempts = 0, accepted = 0, bad = 0, status = 0;
-    bool last_rej = false, need_jac = true;
+    bool last_rej = false, need_f = false;
+    int since_jac = p.jac_every, jac_evals = 0;
     bool done = (p.T_cut > 0.0) && !(T0 >= p.T_cut);
     int64_t ck_chunk = -1;   // kept by wavefront 0, which writes the records
     V2 f1{0.0, 0.0};
@@ -597,9 +620,15 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
       }
       ++attempts;
       const double hs = fmin(h, rem);
-      if (need_jac || !jsv) {
+      // J at every jac_every-th accepted state (and the first), saved; the
+      // LU overwrites it, so in between and after a rejection it is reloaded
+      // (without a saved copy - jac_every is then 1 - evaluated again at the
+      // same state), with f alone at a new state
+      if (since_jac >= p.jac_every || !jsv) {
         f1 = t4_rhs_jac(M, P, phi, L, p.lnA);
-        need_jac = false;
+        since_jac = 0;
+        need_f = false;
+        ++jac_evals;
         if (jsv && tid < N)
           for (int i = 0; i < N; ++i) jsv[i * N + tid] = L.J[i * ldj + tid];
       } else {
@@ -607,6 +636,10 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
         if (tid < N)
           for (int i = 0; i < N; ++i) L.J[i * ldj + tid] = jsv[i * N + tid];
         wsync();
+        if (need_f) {
+          f1 = t4_rhs(M, P, phi, L, p.lnA);
+          need_f = false;
+        }
       }
       const RosTable& R = p.tab;
       const int rc = t4_lu(L.J, ldj, N, 1.0 / (hs * R.gamma), L);
@@ -676,7 +709,8 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
           }
         }
         phi = ynew;
-        need_jac = true;
+        ++since_jac;
+        need_f = true;
         rem -= hs;
         ++accepted;
         fac = fmin(p.fac_max, fmax(p.fac_min, fac));
@@ -725,6 +759,7 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
           atomicAdd(&p.stats[0], (unsigned long long)attempts);
           atomicAdd(&p.stats[1], (unsigned long long)accepted);
           atomicAdd(&p.stats[2], (unsigned long long)(attempts - accepted));
+          atomicAdd(&p.stats[3], (unsigned long long)jac_evals);
         }
       }
     }
@@ -1215,6 +1250,7 @@ void chem_opts_default(chem_opts* o) {
   o->method = CHEM_METHOD_ROS4;
   o->estimator = CHEM_EST_EMBEDDED;
   o->team_waves = 0;
+  o->jac_every = 1;
   o->stats = nullptr;
 }
 
@@ -1426,6 +1462,7 @@ int chem_integrate(chem_mech_t m, int64_t n, const double* T_in, const double* P
   int rc = resolve_opts(m, n, opts, &ro);
   if (rc) return fail(rc);
   c->method = ro.method;
+  if (ro.jac_every > 1) return fail(CHEM_EUNSUPPORTED);   // the adjoint re-evaluates J at every record
   double per_cell;
   {
     std::lock_guard<std::mutex> g(m->mu);
@@ -1525,6 +1562,7 @@ int chem_integrate_noalloc(chem_mech_t m, int64_t n, const double* T_in, const d
   if (o.method < 0 || o.method >= N_METHODS) return CHEM_EINVAL;
   if (o.estimator != CHEM_EST_EMBEDDED && o.estimator != CHEM_EST_FILTERED) return CHEM_EINVAL;
   if (o.team_waves != 0 && o.team_waves != 1 && o.team_waves != 4) return CHEM_EINVAL;
+  if (o.jac_every < 0) return CHEM_EINVAL;
   if ((o.team_waves == 1 && m->view.N > 64) || (o.team_waves == 4 && m->view.N <= 64)) return CHEM_EUNSUPPORTED;
   if (o.wg_size < 0 || o.wg_size > 256 || (o.wg_size % 64) != 0) return CHEM_EINVAL;
   if (n == 0) return CHEM_OK;
@@ -1600,6 +1638,7 @@ static IntParams make_params(chem_mech_t m, const chem_opts& o, int64_t n, const
   p.T_cut = o.T_cut;
   p.max_steps = o.max_steps;
   p.estimator = o.estimator;
+  p.jac_every = o.jac_every > 0 ? o.jac_every : 1;
   p.tab = TABLES[o.method];
   p.h_io = h_io;
   p.n_steps = n_steps;
@@ -1619,6 +1658,8 @@ static int team_launch(chem_mech_t m, const chem_opts& o, IntParams p, bool pers
   const bool four = N > 64;             // four wavefronts per cell (N <= 128)
   TeamKernel kern = four ? integrate_team4_kernel : team_kernel(N);
   if (!kern) return CHEM_EUNSUPPORTED;
+  // four wavefronts per cell keep J only through the persistent grid's saved copies
+  if (four && p.jac_every > 1 && !(persistent && jsave_ws)) return CHEM_EUNSUPPORTED;
   const int threads = four ? T4_THREADS : 64;
   const size_t lds = (four ? Team4Lds::doubles(N) : TeamLds::doubles(N)) * sizeof(double);
   if (lds > 65536)   // above the default dynamic-LDS limit of a launch
@@ -1663,6 +1704,7 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
   if (o.method < 0 || o.method >= N_METHODS) return CHEM_EINVAL;
   if (o.estimator != CHEM_EST_EMBEDDED && o.estimator != CHEM_EST_FILTERED) return CHEM_EINVAL;
   if (o.team_waves != 0 && o.team_waves != 1 && o.team_waves != 4) return CHEM_EINVAL;
+  if (o.jac_every < 0) return CHEM_EINVAL;
   if (n == 0) return CHEM_OK;
   HIPCHECK(hipSetDevice(m->device));
   int mode = o.mode;

@@ -142,27 +142,51 @@ struct RateOutT {
 };
 using RateOut = RateOutT<double>;
 
-template <class S>
-__device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S T, S lnT, S iT,
-                                                     S ctot, LaneT<S> conc, LaneT<S> gib,
-                                                     LaneT<S> hrt, const double* __restrict__ lnA_over,
-                                                     bool want_deriv) {
+// The per-reaction fields reaction_rate reads, loaded in one go so that a
+// loop over reactions can fetch the next reaction's record while it works on
+// the current one.
+struct RxnRec {
+  int type, nr, np, e0, e1, fo;
+  int sp[6], nu[6];   // all six slots (unused ones hold 0)
+  double lnA, b, th, dnu;
+};
+
+__device__ __forceinline__ RxnRec load_rxn(const MechView& M, int j, const double* __restrict__ lnA_over) {
   const int32_t* info = M.rinfo + 8 * j;
   const int32_t* sp = M.rspec + 6 * j;
   const int32_t* nu = M.rnu + 6 * j;
   const double* ar = M.arr + 4 * j;
-  // Every field of the reaction is read up front and unconditionally (all six
-  // species slots exist, unused ones hold 0), so the loads overlap instead of
-  // following the data-dependent control flow one round trip at a time.
+  RxnRec r;
+  r.type = info[0];
+  r.nr = info[1];
+  r.np = info[2];
+  r.e0 = info[3];
+  r.e1 = info[4];
+  r.fo = info[5];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    r.sp[q] = sp[q];
+    r.nu[q] = nu[q];
+  }
+  r.lnA = lnA_over ? lnA_over[M.rorig[j]] : ar[0];
+  r.b = ar[1];
+  r.th = ar[2];
+  r.dnu = ar[3];
+  return r;
+}
+
+template <class S>
+__device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, const RxnRec& R, S T, S lnT, S iT,
+                                                     S ctot, LaneT<S> conc, LaneT<S> gib,
+                                                     LaneT<S> hrt, bool want_deriv) {
   int spv[6], nuv[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    spv[q] = sp[q];
-    nuv[q] = nu[q];
+    spv[q] = R.sp[q];
+    nuv[q] = R.nu[q];
   }
-  const int type = info[0], nr = info[1], np = info[2];
-  const double lnA = lnA_over ? lnA_over[M.rorig[j]] : ar[0];
-  const double b = ar[1], th = ar[2], dnu = ar[3];
+  const int type = R.type, nr = R.nr, np = R.np;
+  const double lnA = R.lnA, b = R.b, th = R.th, dnu = R.dnu;
   S cq[6], gq[6], hq[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
@@ -176,22 +200,30 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S
   S k = kinf, dlnk = dlnkinf, dk_dM = sc<S>(0.0);
   if (type != RX_ELEM) {
     // [M] = sum C + sum (alpha - 1) C over the listed efficiencies: the first
-    // four unrolled (loads issued together), any further ones in a loop
+    // four unrolled - their table entries, then their concentrations, each
+    // group issued together - any further ones in a loop
     S Mc = ctot;
-    const int e0 = info[3], e1 = info[4];
+    const int e0 = R.e0, e1 = R.e1;
+    int ei[4];
+    double ea[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = (e0 + t < e1) ? e0 + t : e0;   // in the table, or its padding when e0 == e1
-      const double am1 = M.eff_am1[e];
-      const S c = conc[M.eff_idx[e]];
-      if (e0 + t < e1) Mc += am1 * c;
+      ei[t] = M.eff_idx[e];
+      ea[t] = M.eff_am1[e];
     }
+    S ec[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ec[t] = conc[ei[t]];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (e0 + t < e1) Mc += ea[t] * ec[t];
     for (int e = e0 + 4; e < e1; ++e) Mc += M.eff_am1[e] * conc[M.eff_idx[e]];
     if (type == RX_THIRD) {
       k = kinf * Mc;
       dk_dM = kinf;
     } else {
-      const double* f = M.fo + 8 * info[5];
+      const double* f = M.fo + 8 * R.fo;
       const S lnk0 = lnA + f[0] + f[1] * lnT - f[2] * iT;
       const S k0 = exp(lnk0);
       const S dlnk0 = (f[1] + f[2] * iT) * iT;
@@ -265,6 +297,15 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S
   o.dlnKc_dT = (sh - dnu) * iT;
   o.beta = dk_dM * (rf - rr * exp(-lnKc));
   return o;
+}
+
+// The same for reaction j, its record loaded here.
+template <class S>
+__device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, int j, S T, S lnT, S iT,
+                                                     S ctot, LaneT<S> conc, LaneT<S> gib,
+                                                     LaneT<S> hrt, const double* __restrict__ lnA_over,
+                                                     bool want_deriv) {
+  return reaction_rate(M, load_rxn(M, j, lnA_over), T, lnT, iT, ctot, conc, gib, hrt, want_deriv);
 }
 
 // Concentrations from Phi; returns the sum over all K species.

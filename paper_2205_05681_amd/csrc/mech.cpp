@@ -9,10 +9,12 @@
 // SI units (kmol, m3, s, K); theta = Ea / R.
 #include "mech.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
 #include <sstream>
+#include <tuple>
 
 #include "../../include/chem.h"
 
@@ -117,10 +119,16 @@ int parse_mechanism(const char* path, HostMech& m) {
 }
 
 void group_reactions_by_type(HostMech& m) {
-  std::vector<int32_t> order;
-  for (int t = RX_ELEM; t <= RX_TROE; ++t)
-    for (int j = 0; j < m.Nr; ++j)
-      if (m.rinfo[(size_t)j * 8] == t) order.push_back(j);
+  // by type, then by the number of participants (reactants + products,
+  // then reactants), file order within: the lanes of a wavefront then mostly
+  // use the same species slots
+  std::vector<int32_t> order(m.Nr);
+  for (int j = 0; j < m.Nr; ++j) order[j] = j;
+  auto key = [&](int j) {
+    const int32_t* in = &m.rinfo[(size_t)j * 8];
+    return std::make_tuple(in[0], in[1] + in[2], in[1]);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
   HostMech r = m;
   for (int jn = 0; jn < m.Nr; ++jn) {
     const int j = order[jn];

@@ -8,8 +8,12 @@
 //
 // The values are the published ones of the references the table gives: ROS3
 // and RODAS3 from Sandu et al. (1997); ROS4 - Hairer and Wanner's L-stable
-// set - and RODAS4 from Hairer and Wanner, Solving ODEs II.  `elo` is the
-// order of the estimate's leading term, the exponent of the step-size rule.
+// set - and RODAS4 from Hairer and Wanner, Solving ODEs II.  ROS34PW2 (Rang
+// and Angermann 2005) is a W-method, the paper's future work: its order
+// conditions hold for any matrix in the place of J, so the Jacobian may be
+// kept over several steps; it is published in the standard form and
+// transformed here at compile time.  `elo` is the order of the estimate's
+// leading term, the exponent of the step-size rule.
 // `newf[i]` is 0 when stage i's argument equals stage i-1's (row i of a equal
 // to row i-1), so that stage reuses the previous f.
 #pragma once
@@ -28,7 +32,74 @@ struct RosTable {
   int newf[MAX_STAGES];
 };
 
-enum MethodId : int { METHOD_ROS4 = 0, METHOD_ROS3 = 1, METHOD_RODAS3 = 2, METHOD_RODAS4 = 3, N_METHODS = 4 };
+enum MethodId : int {
+  METHOD_ROS4 = 0,
+  METHOD_ROS3 = 1,
+  METHOD_RODAS3 = 2,
+  METHOD_RODAS4 = 3,
+  METHOD_ROS34PW2 = 4,
+  N_METHODS = 5
+};
+
+// A method in the standard form: alpha and gamma below the diagonal, gamma on
+// it, weights b and embedded weights bhat.
+struct RosStandard {
+  int s;
+  double gamma, elo;
+  double alpha[MAX_STAGES][MAX_STAGES];
+  double gam[MAX_STAGES][MAX_STAGES];
+  double b[MAX_STAGES], bhat[MAX_STAGES];
+};
+
+// The transformed coefficients: Gamma^-1 column by column (forward
+// substitution), then a = alpha Gamma^-1, c = -Gamma^-1 below the diagonal,
+// m = b Gamma^-1, e = (b - bhat) Gamma^-1.
+constexpr RosTable transform(const RosStandard& f) {
+  RosTable t{};
+  t.s = f.s;
+  t.gamma = f.gamma;
+  t.elo = f.elo;
+  double gi[MAX_STAGES][MAX_STAGES] = {};
+  for (int col = 0; col < f.s; ++col)
+    for (int i = 0; i < f.s; ++i) {
+      double r = (i == col) ? 1.0 : 0.0;
+      for (int j = 0; j < i; ++j) r -= f.gam[i][j] * gi[j][col];
+      gi[i][col] = r / f.gamma;
+    }
+  for (int i = 0; i < f.s; ++i)
+    for (int j = 0; j < i; ++j) {
+      double a = 0.0;
+      for (int l = 0; l < f.s; ++l) a += f.alpha[i][l] * gi[l][j];
+      t.a[i][j] = a;
+      t.c[i][j] = -gi[i][j];
+    }
+  for (int j = 0; j < f.s; ++j) {
+    double m = 0.0, e = 0.0;
+    for (int l = 0; l < f.s; ++l) {
+      m += f.b[l] * gi[l][j];
+      e += (f.b[l] - f.bhat[l]) * gi[l][j];
+    }
+    t.m[j] = m;
+    t.e[j] = e;
+  }
+  for (int i = 0; i < f.s; ++i) {
+    bool same = i > 0;
+    for (int j = 0; j < i && same; ++j) same = t.a[i][j] == (j < i - 1 ? t.a[i - 1][j] : 0.0);
+    t.newf[i] = same ? 0 : 1;
+  }
+  return t;
+}
+
+// ROS34PW2, Rang and Angermann (2005): order 3, embedded 2, stiffly accurate.
+constexpr RosStandard ROS34PW2_STD = {
+    4, 0.435866521508459, 3.0,
+    {{0}, {0.87173304301691801}, {0.84457060015369423, -0.11299064236484185}, {0.0, 0.0, 1.0}},
+    {{0},
+     {-0.87173304301691801},
+     {-0.90338057013044082, 0.054180672388095326},
+     {0.24212380706095346, -1.2232505839045147, 0.54526025533510214}},
+    {0.24212380706095346, -1.2232505839045147, 1.5452602553351020, 0.435866521508459},
+    {0.37810903145819369, -0.096042292212423178, 0.5, 0.2179332607542295}};
 
 constexpr RosTable TABLES[N_METHODS] = {
     // ROS4, Hairer-Wanner L-stable set (gamma is the L-stable root 1/x2 of the
@@ -74,6 +145,7 @@ constexpr RosTable TABLES[N_METHODS] = {
      {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0, 1.0},
      {0.0, 0.0, 0.0, 0.0, 0.0, 1.0},
      {1, 1, 1, 1, 1, 1}},
+    transform(ROS34PW2_STD),
 };
 
 // ROS4 coefficients by name, for the discrete adjoint (which is written for

@@ -202,17 +202,19 @@ __device__ __forceinline__ double team_rhs(const MechView& M, double P, double y
   wsync();
   const double lnT = log(T), iT = 1.0 / T;
   LdsLane conc{L.conc}, gib{L.gib}, hrt{L.hrt};
-  for (int j = lane; j < M.Nr; j += 64) {
-    const RateOut r = reaction_rate(M, j, T, lnT, iT, ctot, Lane{conc.p, 1}, Lane{gib.p, 1},
-                                    Lane{hrt.p, 1}, lnA, false);
-    const int32_t* info = M.rinfo + 8 * j;
-    const int32_t* sp = M.rspec + 6 * j;
-    const int32_t* nu = M.rnu + 6 * j;
-    // slots with compile-time bounds, loads unconditional (unused slots hold 0)
+  // the next reaction's record is fetched while this one is worked on
+  const int Nr = M.Nr;
+  RxnRec nx = load_rxn(M, lane < Nr ? lane : Nr - 1, lnA);
+  for (int j = lane; j < Nr; j += 64) {
+    const RxnRec R = nx;
+    nx = load_rxn(M, j + 64 < Nr ? j + 64 : j, lnA);
+    const RateOut r = reaction_rate(M, R, T, lnT, iT, ctot, Lane{conc.p, 1}, Lane{gib.p, 1},
+                                    Lane{hrt.p, 1}, false);
+    // slots with compile-time bounds (unused slots hold 0)
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-      const int sq = sp[q], nq = nu[q];
-      if ((q < 3) ? (q < info[1]) : (q - 3 < info[2])) atomicAdd(&L.wdot[sq], (q < 3 ? -nq : nq) * r.q);
+      const int sq = R.sp[q], nq = R.nu[q];
+      if ((q < 3) ? (q < R.nr) : (q - 3 < R.np)) atomicAdd(&L.wdot[sq], (q < 3 ? -nq : nq) * r.q);
     }
   }
   wsync();
@@ -255,13 +257,14 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
     L.tb[lane] = sc<S>(0.0);
   }
   wsync();
-  for (int j = lane; j < M.Nr; j += 64) {
-    const RateOutT<S> r = reaction_rate(M, j, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
-                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, lnA, true);
-    const int32_t* info = M.rinfo + 8 * j;
-    const int32_t* sp = M.rspec + 6 * j;
-    const int32_t* nu = M.rnu + 6 * j;
-    const int nr = info[1], np = info[2];
+  const int Nr = M.Nr;
+  RxnRec nx = load_rxn(M, lane < Nr ? lane : Nr - 1, lnA);   // fetched one reaction ahead
+  for (int j = lane; j < Nr; j += 64) {
+    const RxnRec R = nx;
+    nx = load_rxn(M, j + 64 < Nr ? j + 64 : j, lnA);
+    const RateOutT<S> r = reaction_rate(M, R, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
+                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, true);
+    const int nr = R.nr, np = R.np;
     const S dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
     // participant slots 0..2 (reactants) and 3..5 (products), with compile-time
     // bounds: an unused slot has coefficient 0, and its updates go to this
@@ -273,8 +276,8 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       on[q] = (q < 3) ? (q < nr) : (q - 3 < np);
-      ks[q] = sp[q];           // unused slots hold species 0 and coefficient 0
-      nus[q] = nu[q];
+      ks[q] = R.sp[q];         // unused slots hold species 0 and coefficient 0
+      nus[q] = R.nu[q];
       cs[q] = L.conc[ks[q]];
     }
     // d q / d C of slot q: the mass-action product of its side with the power
@@ -310,11 +313,11 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
         lds_add((on[q] && on[t]) ? dst : dummy, vk * dq[t]);
       }
     }
-    if (info[0] != RX_ELEM) {
+    if (R.type != RX_ELEM) {
       // third body and falloff: the uniform [M] part and the efficiency
       // columns; the first four efficiencies are read together up front, any
       // further ones in a loop
-      const int e0 = info[3], e1 = info[4];
+      const int e0 = R.e0, e1 = R.e1;
       int em[4];
       double ea[4];
 #pragma unroll

@@ -14,14 +14,17 @@ step):
     RODAS4 5);
   * the stage combinations and the error norm.
 Per accepted step it also needs f and the analytical Jacobian at the new
-state; a rejected step reuses them.  So for a batch:
-  flops = accepted * F_fJ + attempts * (F_M + F_LU + n_sol F_sol + n_f F_f + F_vec).
+state; a rejected step reuses them.  With the Jacobian kept over several
+steps (a W-method), a new state without a new J needs f alone.  So for a
+batch with E Jacobian evaluations:
+  flops = E * F_fJ + (accepted - E) * F_f
+          + attempts * (F_M + F_LU + n_sol F_sol + n_f F_f + F_vec).
 """
 
 from __future__ import annotations
 
 # stages, new f evaluations per attempt (stage 1 uses the f evaluated with J)
-METHOD_SHAPE = {"ros4": (4, 2), "ros3": (3, 1), "rodas3": (4, 2), "rodas4": (6, 5)}
+METHOD_SHAPE = {"ros4": (4, 2), "ros3": (3, 1), "rodas3": (4, 2), "rodas4": (6, 5), "ros34pw2": (4, 3)}
 
 
 def _thermo(K, with_dcp):
@@ -88,9 +91,11 @@ def step_counts(mech, method="ros4", estimator="embedded"):
                 transcendentals_per_rhs=t_rhs, f_per_attempt=nf)
 
 
-def batch_flops(mech, attempts, accepted, method="ros4", estimator="embedded"):
-    """Algorithmic FP64 flops and transcendental calls of a batch."""
+def batch_flops(mech, attempts, accepted, method="ros4", estimator="embedded", jac_evals=None):
+    """Algorithmic FP64 flops and transcendental calls of a batch (jac_evals:
+    Jacobian evaluations, one per accepted step unless J is kept)."""
     c = step_counts(mech, method, estimator)
-    flops = accepted * c["per_accept"] + attempts * c["per_attempt"]
+    je = accepted if jac_evals is None else jac_evals
+    flops = je * c["per_accept"] + (accepted - je) * c["rhs"] + attempts * c["per_attempt"]
     trans = (accepted + c["f_per_attempt"] * attempts) * c["transcendentals_per_rhs"]
     return flops, trans

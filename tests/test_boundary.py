@@ -59,3 +59,4 @@ def test_opts_struct_layout_matches_the_header():
     o = chem.Opts.from_buffer(buf)
     assert o.stats is None
     assert o.method == 0 and o.estimator == 0 and o.team_waves == 0 and o.order == 1
+    assert o.jac_every == 1

@@ -172,6 +172,61 @@ def test_methods_parity(chem, ch4, method, estimator, mode):
     mech.close()
 
 
+@pytest.mark.parametrize("jac_every", [1, 4])
+@pytest.mark.parametrize("mode", ["plain", "team_persistent"])
+def test_w_method_with_a_kept_jacobian(chem, ch4, jac_every, mode):
+    """ROS34PW2, the W-method, with the Jacobian evaluated at every
+    jac_every-th accepted state and kept in between: 1,000 mixing-layer cells
+    against the oracle running the same policy, and the Jacobian count the
+    launch reports (one at every jac_every-th of a cell's accepted states)."""
+    path, m, o = ch4
+    say("case: ch4 mechanism, 1000 cells, ros34pw2, jac_every", jac_every, mode)
+    T, P, Y = synth.states_mixing(m, 1000, 202)
+    mech = chem.Mechanism(path)
+    stats = torch.zeros(4, dtype=torch.int64, device="cuda")
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode=mode, method="ros34pw2", jac_every=jac_every,
+                                 stats=stats)
+    assert np.all(sg == 0) and np.all(ng >= 1)
+    att, acc, rej, je = (int(x) for x in stats.cpu().numpy())
+    assert acc == ng.sum() and att == acc + rej
+    assert je == int(np.sum((ng + jac_every - 1) // jac_every))
+    r, msg = parity.check_batch(o, T, P, Y, 1e-6, Tg, Yg, ng, "ch4 ros34pw2 jac_every=%d %s" % (jac_every, mode),
+                                method="ros34pw2", jac_every=jac_every)
+    say(msg)
+    mech.close()
+
+
+def test_kept_jacobian_changes_the_steps_and_needs_a_saved_copy(chem, ch4, large):
+    """Keeping J changes the integration (the kept J is used: other results
+    than jac_every = 1); with four wavefronts per cell a kept J needs
+    the persistent launch's saved copies, and a checkpoint needs a fresh J at
+    every step - both refused otherwise."""
+    path, m, o = ch4
+    T, P, Y = synth.states_mixing(m, 256, 202)
+    mech = chem.Mechanism(path)
+    a = run_gpu(chem, mech, T, P, Y, 1e-6, mode="team_persistent", method="ros34pw2", jac_every=1)
+    b = run_gpu(chem, mech, T, P, Y, 1e-6, mode="team_persistent", method="ros34pw2", jac_every=3)
+    assert not np.array_equal(a[0], b[0])
+    with pytest.raises(chem.ChemError) as e:
+        chem.integrate(mech, dev(T), dev(P), dev(Y), 1e-6, checkpoint=True,
+                       opts=chem.default_opts(method="ros34pw2", jac_every=2))
+    assert e.value.code == chem.EUNSUPPORTED
+    mech.close()
+    lpath, lm, lo = large
+    T, P, Y = synth.states_mixing(lm, 64, 204)
+    mech = chem.Mechanism(lpath)
+    with pytest.raises(chem.ChemError) as e:
+        run_gpu(chem, mech, T, P, Y, 1e-6, mode="team", method="ros34pw2", jac_every=2)
+    assert e.value.code == chem.EUNSUPPORTED
+    Tg, Yg, hg, ng, sg = run_gpu(chem, mech, T, P, Y, 1e-6, mode="team_persistent", method="ros34pw2",
+                                 jac_every=2)
+    assert np.all(sg == 0)
+    r, msg = parity.check_batch(lo, T, P, Y, 1e-6, Tg, Yg, ng, "large ros34pw2 jac_every=2 team_persistent",
+                                method="ros34pw2", jac_every=2)
+    say(msg)
+    mech.close()
+
+
 @pytest.mark.timeout(900)
 def test_ch4_full_size_all_cells(chem, ch4):
     """65,536 mixing-layer cells in the benchmark's launch (auto), every cell

@@ -10,13 +10,19 @@ the RODAS methods, and observed convergence orders on problems with
 closed-form solutions.  They also pin the error estimators through the
 stability functions of the two solutions, and the step-size controller
 through how work and global error scale with the tolerance.
+
+ROS34PW2 (Rang and Angermann 2005) is the W-method of the paper's future
+work (a Rosenbrock method whose order conditions hold for any matrix in the
+place of J, so that J can be kept over several steps); its extra pins check
+that property: order 3 with a wrong Jacobian and with a Jacobian kept from
+earlier steps, where ROS4 loses its order.
 """
 import numpy as np
 import pytest
 
 import oracle
 
-ORDER = {"ros3": 3, "ros4": 4, "rodas3": 3, "rodas4": 4}
+ORDER = {"ros3": 3, "ros4": 4, "rodas3": 3, "rodas4": 4, "ros34pw2": 3}
 METHODS = list(ORDER)
 
 
@@ -95,15 +101,76 @@ def test_l_stability_and_accuracy_of_the_stability_function(name):
         assert abs(stability(alpha, G, b, z) - np.exp(z)) < 5 * abs(z) ** (p + 1)
 
 
-@pytest.mark.parametrize("name", ["rodas3", "rodas4"])
-def test_rodas_stiffly_accurate(name):
-    """The RODAS solutions (main and embedded) are the last stage arguments:
-    b_i = beta_si, so both damp a stiff mode completely."""
+@pytest.mark.parametrize("name", ["rodas3", "rodas4", "ros34pw2"])
+def test_stiffly_accurate(name):
+    """The RODAS solutions (main and embedded) and the ROS34PW2 main solution
+    are the last stage arguments: b_i = beta_si, so they damp a stiff mode
+    completely."""
     t = oracle.method_table(name)
     g, alpha, G, b, bh = untransform(t)
     B = alpha + G
     assert np.allclose(b, B[-1], atol=1e-13)
-    assert abs(stability(alpha, G, bh, -1e14)) < 1e-9
+    if name != "ros34pw2":
+        assert abs(stability(alpha, G, bh, -1e14)) < 1e-9
+
+
+def test_w_method_order_with_a_wrong_jacobian():
+    """y' = A y with every step using A + E in place of the Jacobian: ROS34PW2
+    keeps order 3 (its W-order conditions), ROS4 falls to order 2 or below."""
+    rng = np.random.default_rng(5)
+    lam = -np.array([1.0, 2.0, 0.5, 3.0])
+    A, Q, y0 = stiff_linear(4, 9, lam)
+    E = 0.5 * rng.normal(size=(4, 4))
+    T = 1.0
+    exact = Q @ (np.exp(lam * T) * (Q.T @ y0))
+
+    def slopes(name, Aj):
+        errs = []
+        for steps in (10, 20, 40, 80):
+            y = y0.copy()
+            for _ in range(steps):
+                y = oracle.linear_step(A, y, T / steps, method=name, Ajac=Aj)[0]
+            errs.append(np.abs(y - exact).max())
+        return np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+
+    assert np.all(np.abs(slopes("ros34pw2", A + E) - 3) < 0.15)
+    assert np.all(np.abs(slopes("ros34pw2", np.zeros((4, 4))) - 3) < 0.15)
+    assert np.all(slopes("ros4", A + E) < 2.3)
+    assert np.all(np.abs(slopes("ros4", A) - 4) < 0.3)       # the exact Jacobian: order 4
+
+
+@pytest.mark.parametrize("jac_every", [2, 5])
+def test_w_method_keeps_its_order_with_a_kept_jacobian(jac_every):
+    """y' = -y^3 with fixed steps and the Jacobian of every jac_every-th
+    step's state kept in between: ROS34PW2 converges at order 3, ROS4 does
+    not keep its order 4."""
+    y0, T = 1.0, 1.0
+    exact = y0 / np.sqrt(1 + 2 * y0 ** 2 * T)
+    n = np.array([20, 40, 80, 160])
+
+    def slope(name):
+        errs = np.array([abs(oracle.integrate_cubic(y0, T, h_fixed=T / k, method=name, jac_every=jac_every)[0]
+                             - exact) for k in n])
+        return -np.polyfit(np.log(n), np.log(errs), 1)[0]
+
+    assert slope("ros34pw2") == pytest.approx(3.0, abs=0.3)
+    assert slope("ros4") < 3.3
+
+
+def test_jacobian_reuse_under_step_control():
+    """Adaptive ROS34PW2 on y' = -y^3 with the Jacobian kept for 1, 3 and 10
+    accepted steps: the global error still tracks the tolerance, and keeping
+    J changes the result (the kept J is really used)."""
+    y0, T = 2.0, 3.0
+    exact = y0 / np.sqrt(1 + 2 * y0 ** 2 * T)
+    for k in (1, 3, 10):
+        tols = 10.0 ** -np.arange(5, 10)
+        errs = [abs(oracle.integrate_cubic(y0, T, rtol=t, atol=t, method="ros34pw2", jac_every=k)[0] - exact)
+                for t in tols]
+        assert np.polyfit(np.log(tols), np.log(errs), 1)[0] == pytest.approx(1.0, abs=0.3), (k, errs)
+    y1 = oracle.integrate_cubic(y0, T, rtol=1e-7, atol=1e-7, method="ros34pw2", jac_every=1)[0]
+    y3 = oracle.integrate_cubic(y0, T, rtol=1e-7, atol=1e-7, method="ros34pw2", jac_every=3)[0]
+    assert y1 != y3
 
 
 def test_embedded_estimate_of_a_four_stage_method():
