@@ -44,9 +44,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# the sources of the headline kernel (the one-wavefront-per-cell integrator):
+# the traffic file's counters stay valid while none of them changes
 KERNEL_SOURCES = ["paper_2205_05681_amd/csrc/integrate.hip", "paper_2205_05681_amd/csrc/team.h",
-                  "paper_2205_05681_amd/csrc/team4.h", "paper_2205_05681_amd/csrc/kinetics.h",
-                  "paper_2205_05681_amd/csrc/methods.h", "paper_2205_05681_amd/csrc/mech.h"]
+                  "paper_2205_05681_amd/csrc/kinetics.h", "paper_2205_05681_amd/csrc/methods.h",
+                  "paper_2205_05681_amd/csrc/mech.h", "paper_2205_05681_amd/csrc/mech.cpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_team_kernel_batching_1048576.json")
 METRIC = "cells/s per split step at rtol 1e-6 (plain vs persistent); adjoint/forward cost"
 

@@ -11,14 +11,14 @@
 //     256 threads (reaction j on thread j mod 256) scattering into LDS with
 //     FP64 LDS atomics, column c on thread c (the T and V rows); sums over
 //     species are wave sums combined through LDS in a fixed order;
-//   * the LU of M = I/(h gamma) - J is split over the wavefronts in a 2 x 2
-//     block layout of the matrix padded to 128 x 128 with identity rows and
-//     columns: wave w holds rows 64 rb + lane (rb = w & 1) and columns
-//     64 hc + j (hc = w >> 1, j < 64) in 64 registers per lane.  At column k
-//     the two wavefronts holding column k each find the largest |a| over their
-//     unused rows (exact, ties to the lowest row), the two candidates meet in
-//     LDS, the pivot row's halves and every row's multiplier go through LDS,
-//     and each wavefront updates its block: two work-group barriers per column;
+//   * the LU of M = I/(h gamma) - J is split over the wavefronts by columns
+//     of the matrix padded to 128 x 128 with identity rows and columns: wave w
+//     holds columns 32 w .. 32 w + 31 of every row, rows lane and 64 + lane in
+//     64 registers per lane.  At column k the wavefront holding it alone finds
+//     the largest |a| over the unused rows (exact, ties to the lowest row) and
+//     the multipliers and puts them in LDS; after one work-group barrier every
+//     wavefront updates its columns right of k, reading the pivot row's
+//     entries from its own registers (v_readlane);
 //   * the triangular solves run in every wavefront on its own copy of the
 //     vector (no barrier), reading the factors from LDS.
 #pragma once
@@ -53,16 +53,15 @@ struct Team4Lds {
   double* dwdV;   // [128]
   double* dummy;  // [256]     target of the unused participant slots of a reaction
   double* red;    // [4][8]    per-wavefront partial sums
-  double* prow;   // [2][64]   the pivot row, by column half
-  double* lcol;   // [2][64]   the multipliers, by row block
+  double* prow;   // [128]     the LU's multipliers, even columns
+  double* lcol;   // [128]     the LU's multipliers, odd columns (follows prow)
   double* rdg;    // [128]     1 / U_kk
-  double* pval;   // [2]       signed pivot candidate of each row block
   double* ust;    // [4][MAX_STAGES][128] stage vectors, one copy per wavefront
-  unsigned* pslot;  // [2][4]  pivot candidates: |a| high word, low word, row, non-finite flag
+  unsigned* pslot;  // [16]    the LU's pivot row, by column parity; its first failure code
   int* perm;        // [128]   the row pivoted at each step
   int* misc;        // [8]     work-queue position broadcast
   static __host__ __device__ size_t doubles(int N) {
-    return (size_t)N * (N + 1) + (N + 1) + 9 * 128 + 256 + 32 + 128 + 128 + 128 + 2 +
+    return (size_t)N * (N + 1) + (N + 1) + 9 * 128 + 256 + 32 + 128 + 128 + 128 +
            4 * MAX_STAGES * 128 + 8 /* pslot */ + 64 /* perm */ + 4 /* misc */ + 1;
   }
   __device__ void bind(double* base, int N) {
@@ -82,8 +81,7 @@ struct Team4Lds {
     prow = red + 32;
     lcol = prow + 128;
     rdg = lcol + 128;
-    pval = rdg + 128;
-    ust = pval + 2;
+    ust = rdg + 128;
     pslot = (unsigned*)(ust + 4 * MAX_STAGES * 128);
     perm = (int*)(pslot + 16);
     misc = perm + 128;
@@ -186,24 +184,24 @@ __device__ __forceinline__ V2 t4_rhs(const MechView& M, double P, const V2& y, T
   wsync();
   const double lnT = log(T), iT = 1.0 / T;
   const int w = t4_wave();
-  for (int j0 = 0; j0 < M.Nr; j0 += T4_THREADS) {
+  const int Nr = M.Nr;
+  RxnRec nx = load_rxn(M, tid < Nr ? tid : 0, lnA);   // fetched one chunk ahead
+  for (int j0 = 0; j0 < Nr; j0 += T4_THREADS) {
     // rates of 256 reactions in parallel, then their scatter one wavefront at a
     // time: the LDS additions of one wavefront come in a fixed order, those of
     // concurrent wavefronts would not, and the sums would vary from run to run
     const int j = j0 + tid;
-    const bool have = j < M.Nr;
-    const int jj = have ? j : 0;
-    const RateOut r = reaction_rate(M, jj, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
-                                    Lane{L.hrt, 1}, lnA, false);
-    const int32_t* info = M.rinfo + 8 * jj;
-    const int32_t* sp = M.rspec + 6 * jj;
-    const int32_t* nu = M.rnu + 6 * jj;
+    const bool have = j < Nr;
+    const RxnRec R = nx;
+    nx = load_rxn(M, j + T4_THREADS < Nr ? j + T4_THREADS : 0, lnA);
+    const RateOut r = reaction_rate(M, R, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
+                                    Lane{L.hrt, 1}, false);
     for (int ph = 0; ph < 4; ++ph) {
       if (w == ph && have) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          const int sq = sp[q], nq = nu[q];
-          if ((q < 3) ? (q < info[1]) : (q - 3 < info[2])) atomicAdd(&L.wdot[sq], (q < 3 ? -nq : nq) * r.q);
+          const int sq = R.sp[q], nq = R.nu[q];
+          if ((q < 3) ? (q < R.nr) : (q - 3 < R.np)) atomicAdd(&L.wdot[sq], (q < 3 ? -nq : nq) * r.q);
         }
       }
       wsync();
@@ -244,18 +242,18 @@ __device__ __forceinline__ V2 t4_rhs_jac(const MechView& M, double P, const V2& 
   }
   wsync();
   const int w = t4_wave();
-  for (int j0 = 0; j0 < M.Nr; j0 += T4_THREADS) {
+  const int Nr = M.Nr;
+  RxnRec nx = load_rxn(M, tid < Nr ? tid : 0, lnA);   // fetched one chunk ahead
+  for (int j0 = 0; j0 < Nr; j0 += T4_THREADS) {
     // rates of 256 reactions in parallel, then their scatter one wavefront at a
     // time (a fixed order of the LDS additions: deterministic sums)
     const int j = j0 + tid;
-    const bool have = j < M.Nr;
-    const int jj = have ? j : 0;
-    const RateOut r = reaction_rate(M, jj, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
-                                    Lane{L.hrt, 1}, lnA, true);
-    const int32_t* info = M.rinfo + 8 * jj;
-    const int32_t* sp = M.rspec + 6 * jj;
-    const int32_t* nu = M.rnu + 6 * jj;
-    const int nr = info[1], np = info[2];
+    const bool have = j < Nr;
+    const RxnRec R = nx;
+    nx = load_rxn(M, j + T4_THREADS < Nr ? j + T4_THREADS : 0, lnA);
+    const RateOut r = reaction_rate(M, R, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
+                                    Lane{L.hrt, 1}, true);
+    const int nr = R.nr, np = R.np;
     const double dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
     double* const dummy = L.dummy + tid;
     int ks[6], nus[6];
@@ -264,8 +262,8 @@ __device__ __forceinline__ V2 t4_rhs_jac(const MechView& M, double P, const V2& 
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       on[q] = (q < 3) ? (q < nr) : (q - 3 < np);
-      ks[q] = sp[q];
-      nus[q] = nu[q];
+      ks[q] = R.sp[q];
+      nus[q] = R.nu[q];
       cs[q] = L.conc[ks[q]];
     }
     double dq[6];
@@ -299,8 +297,8 @@ __device__ __forceinline__ V2 t4_rhs_jac(const MechView& M, double P, const V2& 
         lds_add((on[q] && on[t]) ? dst : dummy, vk * dq[t]);
       }
     }
-    if (info[0] != RX_ELEM) {
-      const int e0 = info[3], e1 = info[4];
+    if (R.type != RX_ELEM) {
+      const int e0 = R.e0, e1 = R.e1;
       int em[4];
       double ea[4];
 #pragma unroll
@@ -405,104 +403,92 @@ __device__ __forceinline__ V2 t4_rhs_jac(const MechView& M, double P, const V2& 
   return f;
 }
 
-// A[j] -= l * pr[j] for J0 <= j < 64, eight columns at a time: the eight
-// loads of the pivot row, then their eight FMAs, with the scheduler kept from
-// hoisting later loads (which would hold the whole pivot row in registers
-// beside the block's row segment).
+// Column-block LU: wave w holds columns 32 w + jj (jj < 32) of rows lane and
+// 64 + lane in A0[jj], A1[jj] (the matrix padded to 128 x 128 with identity
+// rows and columns).  At column KC the wavefront owning it alone finds the
+// pivot (exact largest |a| over the unused rows, ties to the lowest row) and
+// the multipliers, and publishes the pivot row index and the multipliers in
+// LDS (two buffers, alternating with the column parity); after one
+// work-group barrier every wavefront updates its columns right of KC, taking
+// the pivot row's entries from its own registers by v_readlane.
+
+// Rows lane, 64 + lane: A -= l u over the local columns J0..31, u the pivot
+// row (lane pl, second half when ph).
 template <int J0>
-__device__ __forceinline__ void t4_update(double (&A)[64], const double* pr, double l) {
+__device__ __forceinline__ void t4c_update(double (&A0)[32], double (&A1)[32], double l0, double l1, int pl,
+                                           bool ph) {
 #pragma unroll
-  for (int j0 = J0; j0 < 64; j0 += 8) {
-    double u[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-      if (j0 + t < 64) u[t] = pr[j0 + t];
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-      if (j0 + t < 64) A[j0 + t] -= l * u[t];
-    __builtin_amdgcn_sched_barrier(0);
+  for (int jj = J0; jj < 32; ++jj) {
+    const double u = bcast(ph ? A1[jj] : A0[jj], pl);
+    A0[jj] -= l0 * u;
+    A1[jj] -= l1 * u;
   }
 }
 
-// One column step of t4_lu (column KC, a compile-time constant, so that the
-// block's row segment stays in registers), then the later columns.
 template <int KC>
-__device__ __forceinline__ void t4_lu_col(double (&A)[64], Team4Lds& L, int& ord, double& rp_own, int& rc) {
+__device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team4Lds& L, int& ord0, int& ord1) {
   if constexpr (KC < T4_NMAX) {
-    constexpr int HK = KC / 64, KK = KC % 64;
-    const int w = t4_wave(), lane = t4_lane(), tid = t4_tid();
-    const int rb = w & 1, hc = w >> 1;
-    const bool act = ord < 0;
-    // (1) the waves holding column KC: largest |a| over their unused rows
-    if (hc == HK) {
-      const double a = fabs(A[KK]);
-      const unsigned hi = act ? (unsigned)__double2hiint(a) : 0u;
-      const unsigned lo = act ? (unsigned)__double2loint(a) : 0u;
-      const unsigned mhi = wave_max_u32(hi);
-      const bool cand = act && hi == mhi;
-      unsigned long long sel = __ballot(cand);
-      if (__builtin_popcountll(sel) > 1) {
-        const unsigned mlo = wave_max_u32(cand ? lo : 0u);
-        sel = __ballot(cand && lo == mlo);
-      }
-      const bool nonfinite = __any(act && hi >= 0x7FF00000u);
-      const int pl = sel ? __builtin_amdgcn_readfirstlane(__ffsll(sel) - 1) : 0;
-      const unsigned plo = (unsigned)__builtin_amdgcn_readlane((int)lo, pl);
-      const double pv = bcast(A[KK], pl);
+    constexpr int W = KC / 32, KK = KC % 32;
+    const int w = t4_wave(), lane = t4_lane();
+    double* lc = L.prow + 128 * (KC & 1);   // L.prow and L.lcol: two buffers of 128
+    double l0 = 0.0, l1 = 0.0;
+    int p = 0;
+    if (w == W) {
+      const bool act0 = ord0 < 0, act1 = ord1 < 0;
+      const double a0 = fabs(A0[KK]), a1 = fabs(A1[KK]);
+      // the IEEE words of a non-negative double order like the value
+      const unsigned h0 = act0 ? (unsigned)__double2hiint(a0) : 0u, w0 = act0 ? (unsigned)__double2loint(a0) : 0u;
+      const unsigned h1 = act1 ? (unsigned)__double2hiint(a1) : 0u, w1 = act1 ? (unsigned)__double2loint(a1) : 0u;
+      const bool t1 = h1 > h0 || (h1 == h0 && w1 > w0);
+      const unsigned bh = t1 ? h1 : h0, bl = t1 ? w1 : w0;
+      const unsigned mhi = wave_max_u32(bh);
+      const bool cand = bh == mhi;
+      unsigned mlo;
+      const unsigned long long sel = __ballot(cand);
+      if (__builtin_popcountll(sel) > 1)   // several lanes share the high word
+        mlo = wave_max_u32(cand ? bl : 0u);
+      else
+        mlo = (unsigned)__builtin_amdgcn_readlane((int)bl, __builtin_amdgcn_readfirstlane(__ffsll(sel) - 1));
+      // the lowest row with the largest key: the first half, then the second
+      const unsigned long long s0 = __ballot(act0 && h0 == mhi && w0 == mlo);
+      const unsigned long long s1 = __ballot(act1 && h1 == mhi && w1 == mlo);
+      p = __builtin_amdgcn_readfirstlane(s0 ? __ffsll(s0) - 1 : 64 + __ffsll(s1) - 1);
+      const bool nonfinite = __any((act0 && h0 >= 0x7FF00000u) || (act1 && h1 >= 0x7FF00000u));
+      const int code = nonfinite ? 2 : ((mhi | mlo) == 0u ? 1 : 0);
+      const double piv = bcast(p >= 64 ? A1[KK] : A0[KK], p & 63);
+      const double rp = 1.0 / piv;
+      const bool u0 = act0 && p != lane, u1 = act1 && p != 64 + lane;
+      l0 = u0 ? A0[KK] * rp : 0.0;
+      l1 = u1 ? A1[KK] * rp : 0.0;
+      A0[KK] = u0 ? l0 : A0[KK];
+      A1[KK] = u1 ? l1 : A1[KK];
+      lc[lane] = l0;
+      lc[64 + lane] = l1;
       if (lane == 0) {
-        L.pslot[4 * rb + 0] = sel ? mhi : 0u;
-        L.pslot[4 * rb + 1] = sel ? plo : 0u;
-        L.pslot[4 * rb + 2] = sel ? (unsigned)(64 * rb + pl) : 0xFFFFFFFFu;
-        L.pslot[4 * rb + 3] = nonfinite ? 1u : 0u;
-        L.pval[rb] = pv;
+        L.pslot[KC & 1] = (unsigned)p;
+        L.perm[KC] = p;
+        L.rdg[KC] = rp;
+        if (L.pslot[2] == 0u && code) L.pslot[2] = (unsigned)code;   // the first failure in column order
       }
+      // keep the column's values here (not sunk past the later columns)
+      asm volatile("" : "+v"(l0), "+v"(l1));
     }
     wsync();
-    // (2) the larger candidate (ties to row block 0, the lower rows)
-    const unsigned h0 = L.pslot[0], l0 = L.pslot[1], r0 = L.pslot[2];
-    const unsigned h1 = L.pslot[4], l1 = L.pslot[5], r1 = L.pslot[6];
-    const bool nonfinite = (L.pslot[3] | L.pslot[7]) != 0u;
-    const bool take1 = (r0 == 0xFFFFFFFFu) || (r1 != 0xFFFFFFFFu && (h1 > h0 || (h1 == h0 && l1 > l0)));
-    const int p = (int)(take1 ? r1 : r0);
-    const double piv = take1 ? L.pval[1] : L.pval[0];
-    const bool zero = (take1 ? (h1 | l1) : (h0 | l0)) == 0u;
-    const int code = nonfinite ? 2 : (zero ? 1 : 0);
-    rc = (rc == 0) ? code : rc;
-    const double rp = 1.0 / piv;
-    const int myrow = 64 * rb + lane;
-    const bool is_p = myrow == p;
-    const bool upd = act && !is_p;
-    double l = 0.0;
-    if (hc == HK) {
-      l = upd ? A[KK] * rp : 0.0;
-      A[KK] = upd ? l : A[KK];
-      L.lcol[64 * rb + lane] = l;
+    if (w != W) {
+      p = (int)L.pslot[KC & 1];
+      l0 = lc[lane];
+      l1 = lc[64 + lane];
     }
-    if (is_p) {
-      // the pivot row's half of this wave, for the other row block's wave
-#pragma unroll
-      for (int j = 0; j < 64; ++j) L.prow[64 * hc + j] = A[j];
-    }
-    if (tid == 0) {
-      L.perm[KC] = p;
-      L.rdg[KC] = rp;
-    }
-    ord = is_p ? KC : ord;
-    rp_own = is_p ? rp : rp_own;
-    // keep the step's bookkeeping here: left alone, the compiler sinks these
-    // select chains to their use after the last column and keeps every
-    // column's pivot candidates live until then (hundreds of spilled registers)
-    asm volatile("" : "+v"(ord), "+v"(rc), "+v"(rp_own));
-    wsync();
-    // (3) update this wave's block: the columns right of KC
-    if (hc != HK) l = L.lcol[64 * rb + lane];
-    const double* pr = L.prow + 64 * hc;
-    if (hc == 0) {
-      if constexpr (HK == 0) t4_update<KK + 1>(A, pr, l);
-    } else {
-      t4_update<(HK == 1 ? KK + 1 : 0)>(A, pr, l);
-    }
-    t4_lu_col<KC + 1>(A, L, ord, rp_own, rc);
+    ord0 = (p == lane) ? KC : ord0;
+    ord1 = (p == 64 + lane) ? KC : ord1;
+    asm volatile("" : "+v"(ord0), "+v"(ord1));
+    const int pl = p & 63;
+    const bool ph = p >= 64;
+    if (w > W)
+      t4c_update<0>(A0, A1, l0, l1, pl, ph);
+    else if (w == W)
+      t4c_update<KK + 1>(A0, A1, l0, l1, pl, ph);
+    t4c_col<KC + 1>(A0, A1, L, ord0, ord1);
   }
 }
 
@@ -517,32 +503,33 @@ __device__ __forceinline__ void t4_lu_col(double (&A)[64], Team4Lds& L, int& ord
 // untouched unless 0 is returned.
 __device__ __forceinline__ int t4_lu(double* __restrict__ F, int ldj, int N, double d, Team4Lds& L) {
   const int w = t4_wave(), lane = t4_lane();
-  const int rb = w & 1, hc = w >> 1;
-  const int r = 64 * rb + lane;
-  const bool own = r < N;
-  const double* row = F + (own ? r : 0) * ldj + 64 * hc;
-  const int jn = own ? N - 64 * hc : 0;    // entries of M in this lane's segment
-  double A[64];
+  const int r0 = lane, r1 = 64 + lane;
+  const bool own0 = r0 < N, own1 = r1 < N;
+  const double* row0 = F + (own0 ? r0 : 0) * ldj + 32 * w;
+  const double* row1 = F + (own1 ? r1 : 0) * ldj + 32 * w;
+  const int jn0 = own0 ? N - 32 * w : 0, jn1 = own1 ? N - 32 * w : 0;   // entries of M in each row segment
+  double A0[32], A1[32];
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
-    const int c = 64 * hc + j;
-    // the load is unconditional (row[j] lies in this work-group's LDS for every
-    // j < 64) and masked afterwards: a conditional load becomes a branch with a
-    // full LDS wait per entry
-    const double v = row[j];
-    const double f = (j < jn) ? v : 0.0;
-    const double dj = ((c == r) & own) ? d : 0.0;
-    A[j] = ((!own) & (c == r)) ? 1.0 : dj - f;
+  for (int jj = 0; jj < 32; ++jj) {
+    const int c = 32 * w + jj;
+    // unconditional loads (every address lies in this work-group's LDS), masked afterwards
+    const double v0 = row0[jj], v1 = row1[jj];
+    const double f0 = (jj < jn0) ? v0 : 0.0, f1 = (jj < jn1) ? v1 : 0.0;
+    A0[jj] = ((!own0) & (c == r0)) ? 1.0 : (((c == r0) & own0) ? d : 0.0) - f0;
+    A1[jj] = ((!own1) & (c == r1)) ? 1.0 : (((c == r1) & own1) ? d : 0.0) - f1;
   }
-  int ord = -1;
-  double rp_own = 0.0;
-  int rc = 0;
-  t4_lu_col<0>(A, L, ord, rp_own, rc);
+  if (w == 0 && lane == 0) L.pslot[2] = 0u;
+  int ord0 = -1, ord1 = -1;
+  wsync();
+  t4c_col<0>(A0, A1, L, ord0, ord1);
+  wsync();
+  const int rc = (int)L.pslot[2];
   if (rc) return rc;
-  if (own) {
 #pragma unroll
-    for (int j = 0; j < 64; ++j)
-      if (64 * hc + j < N) F[ord * ldj + 64 * hc + j] = A[j];
+  for (int jj = 0; jj < 32; ++jj) {
+    const int c = 32 * w + jj;
+    if (own0 && c < N) F[ord0 * ldj + c] = A0[jj];
+    if (own1 && c < N) F[ord1 * ldj + c] = A1[jj];
   }
   wsync();
   return 0;
