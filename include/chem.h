@@ -64,7 +64,10 @@ extern "C" {
 #define CHEM_MODE_TEAM 3        /* a team per cell: one wavefront (N <= 64) or a work-group of
                                    four (N <= 128); J and LU in LDS and registers */
 #define CHEM_MODE_TEAM_PERSISTENT 4 /* a team per cell, resident grid, work queue.  Above
-                                   N = 128 both team modes run one cell per thread. */
+                                   N = 128 both team modes run one cell per thread, and so
+                                   do they where the four-wavefront work-group's LDS (J plus
+                                   four copies of the stage vectors) exceeds a CU's 160 KB:
+                                   the six-stage CHEM_METHOD_RODAS4 above N = 124. */
 
 /* ---- dispatch order (chem_opts.order) ---------------------------------- */
 #define CHEM_ORDER_INDEX 0      /* cells are taken in index order */
@@ -184,7 +187,9 @@ int chem_integrate(chem_mech_t m, int64_t n_cells, const double* T_in, const dou
  * checkpoint), with the team launches only (one or four wavefronts per cell,
  * N <= 128), mode CHEM_MODE_AUTO, CHEM_MODE_TEAM or CHEM_MODE_TEAM_PERSISTENT
  * (AUTO and an autotuned one-cell-per-thread choice run the persistent team
- * launch; an explicit one-cell-per-thread mode is CHEM_EUNSUPPORTED).  With
+ * launch; an explicit one-cell-per-thread mode, and a team launch whose LDS
+ * exceeds a CU's - CHEM_METHOD_RODAS4 above N = 124 - are
+ * CHEM_EUNSUPPORTED).  With
  * four wavefronts per cell (64 < N <= 128) a rejected step evaluates the
  * Jacobian again instead of reloading a saved copy (the same values, so the
  * results equal chem_integrate's).
@@ -274,6 +279,31 @@ void chem_graph_free(chem_graph_t g);
  * lnA nullable as in chem_integrate.  For testing the pieces of a step. */
 int chem_eval(chem_mech_t m, int64_t n, const double* phi, int64_t ld, const double* P,
               const double* lnA, double* f, double* J, hipStream_t stream);
+
+/* The factorisation every attempted step makes of its stage matrix
+ * (Sec. 2.3: each stage solves a system in M = I/(h gamma) - J), alone: LU
+ * with partial pivoting of M = d I - A for n matrices of order N, by the
+ * integrator's own routines, for testing that piece and timing it.
+ *   A       [N*N][ld] device, read only: element (i, j) of matrix c at
+ *           A[(i*N + j)*ld + c] (the layout of chem_eval's J); ld >= n
+ *   d       the diagonal shift (1 / (h gamma) in a step)
+ *   F       [N*N][ld] device, out: row k holds row k of L left of the diagonal
+ *           (unit diagonal implied) and row k of U from the diagonal on, in
+ *           pivot order: row k of L U is row perm[k] of M
+ *   perm    [N][ld] int32 device, out: the row of M pivoted at step k
+ *   status  [n] int32 device, out: 0, 1 (zero pivot) or 2 (non-finite pivot
+ *           column), the first failure in column order; F and perm of a
+ *           matrix that failed are unspecified
+ *   launch  0: the team launches' factorisation (one wavefront per matrix
+ *           for N <= 64, a work-group of four for 64 < N <= 128; the pivot is
+ *           the largest |M_ik| over the rows not yet used, ties to the lowest
+ *           row of M); 1: the one-cell-per-thread launches' (explicit row
+ *           swaps, ties to the lowest current position, N <= 256)
+ * Errors: CHEM_EINVAL (n < 0, N < 1, ld < n, launch not 0 or 1, a null
+ * pointer with n > 0), CHEM_EUNSUPPORTED (N above the launch's limit),
+ * CHEM_EHIP.  Runs on the current device, asynchronous on `stream`. */
+int chem_lu(int64_t n, int32_t N, const double* A, int64_t ld, double d, double* F, int32_t* perm,
+            int32_t* status, int32_t launch, hipStream_t stream);
 
 /* Human-readable text of a return code. */
 const char* chem_error_string(int code);

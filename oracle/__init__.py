@@ -65,6 +65,8 @@ def lib(path=None):
         L.or_rhs.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
         L.or_jacobian.argtypes = [C.c_void_p, C.c_double, _d, _d, _d]
         L.or_lu_solve.argtypes = [C.c_int, _d, _d, _d]
+        L.or_lu.restype = C.c_int
+        L.or_lu.argtypes = [C.c_int, _d, _d, C.POINTER(C.c_int), _d]
         L.or_method_table.argtypes = [C.c_int, _d]
         L.or_step.argtypes = [C.c_void_p, C.c_double, _d, C.c_double, _d, _d, C.c_int, C.c_int]
         L.or_to_phi.argtypes = [C.c_void_p, C.c_double, C.c_double, _d, _d]
@@ -257,6 +259,21 @@ def lu_solve(A, b):
     if rc:
         raise np.linalg.LinAlgError("singular")
     return x
+
+
+def lu(M):
+    """LU with partial pivoting of the square matrix M: (F, perm, status,
+    margin) - the factors in pivot order (row k: L left of the diagonal, unit
+    diagonal implied, U from the diagonal on; row k of L U is row perm[k] of
+    M), 0/1/2 as the library's status, and the smallest relative gap between a
+    pivot and the runner-up of its column."""
+    M = _f64(M)
+    n = M.shape[0]
+    F = np.zeros_like(M)
+    perm = np.zeros(n, dtype=np.intc)
+    margin = np.zeros(1)
+    rc = lib().or_lu(n, _p(M), _p(F), perm.ctypes.data_as(C.POINTER(C.c_int)), _p(margin))
+    return F, perm.astype(np.int64), int(rc), float(margin[0])
 
 
 def integrate_linear(A, y0, dt, rtol=1e-6, atol=1e-10, h_fixed=0.0, method="ros4", estimator="embedded"):

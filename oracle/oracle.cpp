@@ -276,20 +276,27 @@ void jacobian(const Mech& m, double P, const S* phi, const S* lnA, S* J) {
 
 // ---------------------------------------------------------------- linear algebra
 // In-place LU with partial pivoting (largest magnitude, ties to the lowest
-// row).  Returns 0, or 1 for a zero pivot, 2 for a non-finite column.
+// row position after the earlier swaps).  Returns 0, or 1 for a zero pivot, 2
+// for a non-finite column.  margin (nullable) receives the smallest relative
+// gap, over the steps, between the pivot's magnitude and the runner-up's
+// ((best - second) / best; 1 where a column has one candidate): how far the
+// pivot choices are from a tie.
 template <class S>
-int lu(int n, S* A, int* piv) {
+int lu(int n, S* A, int* piv, double* margin = nullptr) {
+  if (margin) *margin = 1.0;
   for (int k = 0; k < n; ++k) {
     int p = k;
-    double best = std::fabs(val(A[k * n + k]));
+    double best = std::fabs(val(A[k * n + k])), second = 0.0;
     bool finite = std::isfinite(best);
     for (int i = k + 1; i < n; ++i) {
       double v = std::fabs(val(A[i * n + k]));
       finite = finite && std::isfinite(v);
-      if (v > best) { best = v; p = i; }
+      if (v > best) { second = best; best = v; p = i; }
+      else if (v > second) second = v;
     }
     if (!finite) return 2;
     if (!(best > 0.0)) return 1;
+    if (margin && k + 1 < n) *margin = std::min(*margin, (best - second) / best);
     piv[k] = p;
     if (p != k)
       for (int j = 0; j < n; ++j) { S t = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = t; }
@@ -711,6 +718,20 @@ int or_lu_solve(int n, const double* A, const double* b, double* x) {
   for (int i = 0; i < n; ++i) x[i] = b[i];
   lu_solve(n, LU.data(), piv.data(), x);
   return 0;
+}
+
+// LU of an n x n row-major matrix M: F receives the factors in pivot order
+// (row k: L left of the diagonal, unit diagonal implied, U from it on), perm
+// the row of M pivoted at each step (the swap sequence applied to 0..n-1),
+// margin as lu's.  Returns lu's code; F and perm are complete only for 0.
+int or_lu(int n, const double* M, double* F, int* perm, double* margin) {
+  for (int i = 0; i < n * n; ++i) F[i] = M[i];
+  std::vector<int> piv(n);
+  const int rc = lu(n, F, piv.data(), margin);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  if (rc == 0)
+    for (int k = 0; k < n; ++k) std::swap(perm[k], perm[piv[k]]);
+  return rc;
 }
 
 // The transformed table of a method: t[0] = s, t[1] = gamma, t[2] = elo, then

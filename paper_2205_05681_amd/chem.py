@@ -72,6 +72,8 @@ def lib():
                                     C.c_double, C.POINTER(Opts), _vp, _vp]
         L.chem_graph_free.argtypes = [_vp]
         L.chem_eval.argtypes = [_vp, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp, _vp, _vp]
+        L.chem_lu.argtypes = [C.c_int64, C.c_int32, _vp, C.c_int64, C.c_double, _vp, _vp, _vp, C.c_int32,
+                              _vp]
         _lib = L
     return _lib
 
@@ -79,7 +81,7 @@ def lib():
 EXPORTS = ("chem_opts_default", "chem_error_string", "chem_mech_load", "chem_mech_info",
            "chem_mech_free", "chem_integrate", "chem_integrate_adjoint", "chem_ckpt_free", "chem_eval",
            "chem_ckpt_records", "chem_ckpt_export", "chem_graph_create", "chem_graph_launch",
-           "chem_graph_free", "chem_autotune", "chem_integrate_noalloc")
+           "chem_graph_free", "chem_autotune", "chem_integrate_noalloc", "chem_lu")
 
 
 def error_string(code):
@@ -322,6 +324,28 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+LU_LAUNCHES = {"team": 0, "thread": 1}
+
+
+def lu(A, d, launch="team"):
+    """LU with partial pivoting of M = d I - A for n matrices A (N*N, n) (the
+    layout of evaluate's J), by the team launches' routine ("team") or the
+    one-cell-per-thread launches' ("thread").  Returns the factors F (N*N, n)
+    in pivot order, perm (N, n) int32 (the row of M pivoted at each step) and
+    status (n,) int32."""
+    NN, n = A.shape
+    N = int(round(NN ** 0.5))
+    if N * N != NN:
+        raise ValueError("A must have N*N rows")
+    F = torch.empty_like(A)
+    perm = torch.empty((N, n), dtype=torch.int32, device=A.device)
+    status = torch.empty((n,), dtype=torch.int32, device=A.device)
+    rc = lib().chem_lu(n, N, _ptr(A, "A"), n, float(d), _ptr(F, "F"), _ptr(perm, "perm", dtype=torch.int32),
+                       _ptr(status, "status", dtype=torch.int32), LU_LAUNCHES[launch], _stream())
+    _check(rc, "chem_lu")
+    return F, perm, status
 
 
 def evaluate(mech, phi, P, lnA=None, jacobian=True):

@@ -573,8 +573,8 @@ __global__ void __launch_bounds__(256) integrate_team4_kernel(IntParams p, bool 
   const int N = M.N, K = M.K, ldj = N + 1;
   const int tid = t4_tid(), w = t4_wave(), lane = t4_lane();
   Team4Lds L;
-  L.bind(lds_raw, N);
-  double* const ust = L.ust + w * (MAX_STAGES * 128);   // this wavefront's stage vectors
+  L.bind(lds_raw, N, p.tab.s);
+  double* const ust = L.ust + w * (p.tab.s * 128);   // this wavefront's stage vectors
   double* const jsv = p.jsave ? p.jsave + (int64_t)blockIdx.x * N * N : nullptr;
   int64_t q;
   if (PERSISTENT) {
@@ -964,6 +964,74 @@ __global__ void eval_kernel(MechView M, int64_t n, const double* __restrict__ ph
   for (int i = 0; i < N; ++i) f_out[(int64_t)i * ldp + c] = f[i];
 }
 
+// ---- the factorisation of a stage matrix alone, M = d I - A, by each
+// launch's own routine; matrix c's element (i, j) at [(i * N + j) * ld + c].
+// The factors leave in pivot order, perm[k] the row of M pivoted at step k.
+
+// One matrix per thread (lu_factor: explicit row swaps), the swap sequence
+// turned into the permutation afterwards.
+__global__ void lu_thread_kernel(int64_t n, int N, const double* __restrict__ A, int64_t ld, double d,
+                                 double* __restrict__ F, int32_t* __restrict__ perm,
+                                 int32_t* __restrict__ status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  Lane a{F + c, ld};
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) a[i * N + j] = (i == j ? d : 0.0) - A[(int64_t)(i * N + j) * ld + c];
+  const int rc = lu_factor(a, perm + c, ld, N);
+  status[c] = rc;
+  if (rc) return;
+  int q[MAX_SPECIES + 1];
+  for (int k = 0; k < N; ++k) q[k] = k;
+  for (int k = 0; k < N; ++k) {
+    const int s = perm[(int64_t)k * ld + c], t = q[k];
+    q[k] = q[s];
+    q[s] = t;
+  }
+  for (int k = 0; k < N; ++k) perm[(int64_t)k * ld + c] = q[k];
+}
+
+// One wavefront per matrix (team_lu_reg), N <= NMAX <= 64: J staged in LDS
+// with the integrator's row stride N + 1.
+template <int NMAX>
+__global__ void __launch_bounds__(64) lu_team_kernel(int64_t n, int N, const double* __restrict__ A,
+                                                     int64_t ld, double d, double* __restrict__ F,
+                                                     int32_t* __restrict__ perm, int32_t* __restrict__ status) {
+  extern __shared__ double lds_raw[];
+  const int lane = threadIdx.x, ldj = N + 1;
+  const int64_t c = blockIdx.x;
+  for (int e = lane; e < N * N; e += 64) lds_raw[(e / N) * ldj + e % N] = A[(int64_t)e * ld + c];
+  wsync();
+  RegLU<NMAX> R;
+  const int rc = team_lu_reg<NMAX>(lds_raw, ldj, N, d, R);
+  if (lane == 0) status[c] = rc;
+  if (rc) return;
+  if (lane < N) {   // every row of M was pivoted at a step < N
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+      if (j < N) F[(int64_t)(R.ord * N + j) * ld + c] = R.A[j];
+    perm[(int64_t)lane * ld + c] = R.pv;
+  }
+}
+
+// A work-group of four wavefronts per matrix (t4_lu), 64 < N <= 128.
+__global__ void __launch_bounds__(256) lu_team4_kernel(int64_t n, int N, const double* __restrict__ A,
+                                                       int64_t ld, double d, double* __restrict__ F,
+                                                       int32_t* __restrict__ perm, int32_t* __restrict__ status) {
+  extern __shared__ double lds_raw[];
+  Team4Lds L;
+  L.bind(lds_raw, N, 1);
+  const int tid = t4_tid(), ldj = N + 1;
+  const int64_t c = blockIdx.x;
+  for (int e = tid; e < N * N; e += T4_THREADS) L.J[(e / N) * ldj + e % N] = A[(int64_t)e * ld + c];
+  wsync();
+  const int rc = t4_lu(L.J, ldj, N, d, L);
+  if (tid == 0) status[c] = rc;
+  if (rc) return;
+  for (int e = tid; e < N * N; e += T4_THREADS) F[(int64_t)e * ld + c] = L.J[(e / N) * ldj + e % N];
+  for (int k = tid; k < N; k += T4_THREADS) perm[(int64_t)k * ld + c] = L.perm[k];
+}
+
 __global__ void reset_counter_kernel(unsigned int* q) { *q = 0u; }
 
 // ---- dispatch order: counting sort of the cells by a temperature bucket,
@@ -1069,6 +1137,7 @@ struct chem_mech_s {
   void* blob = nullptr;
   int device = 0;
   int n_cu = 0;
+  size_t max_lds = 0;               // LDS of a CU: the most one work-group can take
   std::mutex mu;
   std::map<hipStream_t, Workspace> ws;
   std::map<int, chem_opts> tuned;   // batch-size bucket -> autotuned options
@@ -1229,6 +1298,16 @@ TeamKernel team_kernel(int N) {
   return nullptr;
 }
 
+// Whether a team launch (one or four wavefronts per cell) can run a method of
+// s stages: N <= 128, and the work-group's LDS within a CU's (the four-wavefront
+// layout holds four copies of the s stage vectors besides the N x (N + 1) J).
+bool team_fits(chem_mech_t m, int s) {
+  const int N = m->view.N;
+  if (N > T4_NMAX) return false;
+  const size_t lds = (N > 64 ? Team4Lds::doubles(N, s) : TeamLds::doubles(N)) * sizeof(double);
+  return lds <= m->max_lds;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1289,6 +1368,7 @@ int chem_mech_load(const char* path, int device, chem_mech_t* out) {
     return CHEM_EHIP;
   }
   m->n_cu = prop.multiProcessorCount;
+  m->max_lds = prop.maxSharedMemoryPerMultiProcessor;
   {
     unsigned int* sp;   // set up the no-allocation entry point's scratch on this device
     (void)scratch_address(device, &sp);
@@ -1373,6 +1453,34 @@ int chem_eval(chem_mech_t m, int64_t n, const double* phi, int64_t ld, const dou
   const int wg = 64;
   hipLaunchKernelGGL(eval_kernel, dim3((unsigned)((n + wg - 1) / wg)), dim3(wg), 0, stream, m->view,
                      n, phi, ld, P, lnA, f, J, w->ws, slots);
+  HIPCHECK(hipGetLastError());
+  return CHEM_OK;
+}
+
+int chem_lu(int64_t n, int32_t N, const double* A, int64_t ld, double d, double* F, int32_t* perm,
+            int32_t* status, int32_t launch, hipStream_t stream) {
+  if (n < 0 || n > INT32_MAX || N < 1 || ld < n || (launch != 0 && launch != 1)) return CHEM_EINVAL;
+  if (n > 0 && (!A || !F || !perm || !status)) return CHEM_EINVAL;
+  if (N > (launch == 0 ? T4_NMAX : MAX_SPECIES + 1)) return CHEM_EUNSUPPORTED;
+  if (n == 0) return CHEM_OK;
+  if (launch == 1) {
+    hipLaunchKernelGGL(lu_thread_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, stream, n, (int)N, A,
+                       ld, d, F, perm, status);
+  } else if (N <= 64) {
+    decltype(&lu_team_kernel<64>) kern = N <= 16   ? lu_team_kernel<16>
+                                        : N <= 32 ? lu_team_kernel<32>
+                                        : N <= 48 ? lu_team_kernel<48>
+                                        : N <= 56 ? lu_team_kernel<56>
+                                                  : lu_team_kernel<64>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)n), dim3(64), (size_t)N * (N + 1) * sizeof(double), stream, n,
+                       (int)N, A, ld, d, F, perm, status);
+  } else {
+    const size_t lds = Team4Lds::doubles(N, 1) * sizeof(double);
+    HIPCHECK(hipFuncSetAttribute((const void*)lu_team4_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds));
+    hipLaunchKernelGGL(lu_team4_kernel, dim3((unsigned)n), dim3(T4_THREADS), lds, stream, n, (int)N, A, ld, d,
+                       F, perm, status);
+  }
   HIPCHECK(hipGetLastError());
   return CHEM_OK;
 }
@@ -1547,7 +1655,6 @@ int chem_integrate_noalloc(chem_mech_t m, int64_t n, const double* T_in, const d
   if (!m || n < 0 || n > NOALLOC_MAX_CELLS) return CHEM_EINVAL;
   if (n > 0 && (!T_in || !P || !Y_in || !T_out || !Y_out)) return CHEM_EINVAL;
   if (!(dt > 0) || !(rtol > 0) || !(atol >= 0) || ldY < n) return CHEM_EINVAL;
-  if (m->view.N > T4_NMAX) return CHEM_EUNSUPPORTED;
   chem_opts o;
   resolve_opts(m, n, opts, &o);
   if (o.mode < CHEM_MODE_AUTO || o.mode > CHEM_MODE_TEAM_PERSISTENT) return CHEM_EINVAL;
@@ -1563,6 +1670,7 @@ int chem_integrate_noalloc(chem_mech_t m, int64_t n, const double* T_in, const d
   if (o.estimator != CHEM_EST_EMBEDDED && o.estimator != CHEM_EST_FILTERED) return CHEM_EINVAL;
   if (o.team_waves != 0 && o.team_waves != 1 && o.team_waves != 4) return CHEM_EINVAL;
   if (o.jac_every < 0) return CHEM_EINVAL;
+  if (!team_fits(m, TABLES[o.method].s)) return CHEM_EUNSUPPORTED;
   if ((o.team_waves == 1 && m->view.N > 64) || (o.team_waves == 4 && m->view.N <= 64)) return CHEM_EUNSUPPORTED;
   if (o.wg_size < 0 || o.wg_size > 256 || (o.wg_size % 64) != 0) return CHEM_EINVAL;
   if (n == 0) return CHEM_OK;
@@ -1661,7 +1769,7 @@ static int team_launch(chem_mech_t m, const chem_opts& o, IntParams p, bool pers
   // four wavefronts per cell keep J only through the persistent grid's saved copies
   if (four && p.jac_every > 1 && !(persistent && jsave_ws)) return CHEM_EUNSUPPORTED;
   const int threads = four ? T4_THREADS : 64;
-  const size_t lds = (four ? Team4Lds::doubles(N) : TeamLds::doubles(N)) * sizeof(double);
+  const size_t lds = (four ? Team4Lds::doubles(N, p.tab.s) : TeamLds::doubles(N)) * sizeof(double);
   if (lds > 65536)   // above the default dynamic-LDS limit of a launch
     HIPCHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   unsigned grid = (unsigned)p.n;
@@ -1708,8 +1816,9 @@ static int integrate_impl(chem_mech_t m, int64_t n, const double* T_in, const do
   if (n == 0) return CHEM_OK;
   HIPCHECK(hipSetDevice(m->device));
   int mode = o.mode;
-  // one or four wavefronts per cell need N <= 128; larger mechanisms use one cell per thread
-  const bool team_ok = m->view.N <= T4_NMAX;
+  // one or four wavefronts per cell need N <= 128 and their LDS within a CU's;
+  // other mechanisms use one cell per thread
+  const bool team_ok = team_fits(m, TABLES[o.method].s);
   if (o.team_waves != 0 && !team_ok) return CHEM_EUNSUPPORTED;
   if (o.team_waves == 1 && m->view.N > 64) return CHEM_EUNSUPPORTED;
   if (o.team_waves == 4 && m->view.N <= 64) return CHEM_EUNSUPPORTED;
@@ -1906,12 +2015,12 @@ int chem_autotune(chem_mech_t m, int64_t n, const double* T_in, const double* P,
   if (N <= 64) {
     add(CHEM_MODE_TEAM, 0, 0);
     for (int w : {0, 2, 3, 4}) add(CHEM_MODE_TEAM_PERSISTENT, 0, w);
-  } else if (N <= T4_NMAX) {
+  } else if (team_fits(m, TABLES[METHOD_ROS4].s)) {
     // four wavefronts per cell, one work-group per CU (its LDS)
     add(CHEM_MODE_TEAM, 0, 0);
     add(CHEM_MODE_TEAM_PERSISTENT, 0, 0);
   }
-  if (N <= 16 || N > T4_NMAX) {
+  if (N <= 16 || !team_fits(m, TABLES[METHOD_ROS4].s)) {
     add(CHEM_MODE_PLAIN, 64, 0);
     add(CHEM_MODE_PLAIN, 256, 0);
     add(CHEM_MODE_PERSISTENT, 64, 0);

@@ -426,22 +426,28 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
   return f;
 }
 
-// Largest of a non-negative 32-bit key over the 64 lanes (DPP inside rows,
-// each step one v_max_u32 with a DPP source, then the four rows by
-// v_readlane).
+// Largest of a non-negative 32-bit key over the 64 lanes: the row maximum by
+// DPP inside each 16-lane row (every lane of a row ends with it), then the
+// last lane of row 0 into row 1 and of row 2 into row 3 (row_bcast:15, rows 1
+// and 3 written), then the last lane of row 1 into rows 2 and 3
+// (row_bcast:31), so that lane 63 holds the wave maximum: one v_readlane
+// instead of four and a scalar tree.
 __device__ __forceinline__ unsigned umax32(unsigned a, unsigned b) { return a > b ? a : b; }
 template <int CTRL>
 __device__ __forceinline__ unsigned dpp32(unsigned v) {
   return (unsigned)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
+constexpr int DPP_ROW_BCAST15 = 0x142;
+constexpr int DPP_ROW_BCAST31 = 0x143;
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
   v = umax32(v, dpp32<DPP_QUAD_1032>(v));
   v = umax32(v, dpp32<DPP_QUAD_2301>(v));
   v = umax32(v, dpp32<DPP_ROW_HALF_MIRROR>(v));
   v = umax32(v, dpp32<DPP_ROW_MIRROR>(v));
-  const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
-  const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
-  return umax32(umax32(a, b), umax32(c, d));
+  // rows not written by a broadcast keep their own value (the "old" operand)
+  v = umax32(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_BCAST15, 0xA, 0xF, false));
+  v = umax32(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_ROW_BCAST31, 0xC, 0xF, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // One column step of team_lu (column KC, a compile-time constant so that the
@@ -459,6 +465,9 @@ __device__ __forceinline__ void team_lu_col(double (&A)[NMAX], int& ord, double&
     // of a non-negative double order like the value, high word first (the low
     // words are compared only when the high words tie)
     const double a = fabs(A[KC]);
+    // every lane's reciprocal, computed while the pivot is searched (the
+    // pivot lane's is 1 / pivot, the same division as after the search)
+    const double ra = 1.0 / A[KC];
     const unsigned hi = act ? (unsigned)__double2hiint(a) : 0u;
     const unsigned lo = (unsigned)__double2loint(a);
     const unsigned mhi = wave_max_u32(hi);
@@ -470,10 +479,10 @@ __device__ __forceinline__ void team_lu_col(double (&A)[NMAX], int& ord, double&
     }
     const int p = __builtin_amdgcn_readfirstlane(__ffsll(sel) - 1);   // ties: lowest lane
     const bool nonfinite = __any(act && hi >= 0x7FF00000u);
-    const bool zero = mhi == 0u && __builtin_amdgcn_readlane((int)lo, p) == 0;   // largest |a| is 0
+    const bool zero = (mhi == 0u) & (__builtin_amdgcn_readlane((int)lo, p) == 0);   // largest |a| is 0
     const int code = nonfinite ? 2 : (zero ? 1 : 0);
     rc = (rc == 0) ? code : rc;
-    const double rp = 1.0 / bcast(A[KC], p);
+    const double rp = bcast(ra, p);
     const bool is_p = lane == p;
     const bool upd = act && !is_p;
     const double l = upd ? A[KC] * rp : 0.0;

@@ -51,20 +51,21 @@ struct Team4Lds {
   double* tb;     // [128]     uniform third-body part per row
   double* dwdT;   // [128]
   double* dwdV;   // [128]
-  double* dummy;  // [256]     target of the unused participant slots of a reaction
+  double* dummy;  // [256]     target of the unused participant slots of a reaction: the
+                  //           LU's prow and lcol (the two are never in use together)
   double* red;    // [4][8]    per-wavefront partial sums
   double* prow;   // [128]     the LU's multipliers, even columns
   double* lcol;   // [128]     the LU's multipliers, odd columns (follows prow)
   double* rdg;    // [128]     1 / U_kk
-  double* ust;    // [4][MAX_STAGES][128] stage vectors, one copy per wavefront
+  double* ust;    // [4][s][128] stage vectors, one copy per wavefront (s: the method's stages)
   unsigned* pslot;  // [16]    the LU's pivot row, by column parity; its first failure code
   int* perm;        // [128]   the row pivoted at each step
   int* misc;        // [8]     work-queue position broadcast
-  static __host__ __device__ size_t doubles(int N) {
-    return (size_t)N * (N + 1) + (N + 1) + 9 * 128 + 256 + 32 + 128 + 128 + 128 +
-           4 * MAX_STAGES * 128 + 8 /* pslot */ + 64 /* perm */ + 4 /* misc */ + 1;
+  static __host__ __device__ size_t doubles(int N, int s) {
+    return (size_t)N * (N + 1) + (N + 1) + 9 * 128 + 32 + 128 + 128 + 128 + 4 * (size_t)s * 128 +
+           8 /* pslot */ + 64 /* perm */ + 4 /* misc */ + 1;
   }
-  __device__ void bind(double* base, int N) {
+  __device__ void bind(double* base, int N, int s) {
     J = base;
     brow = J + (size_t)N * (N + 1);
     conc = brow + (N + 1);
@@ -76,13 +77,13 @@ struct Team4Lds {
     tb = gb + 128;
     dwdT = tb + 128;
     dwdV = dwdT + 128;
-    dummy = dwdV + 128;
-    red = dummy + 256;
+    red = dwdV + 128;
     prow = red + 32;
     lcol = prow + 128;
+    dummy = prow;
     rdg = lcol + 128;
     ust = rdg + 128;
-    pslot = (unsigned*)(ust + 4 * MAX_STAGES * 128);
+    pslot = (unsigned*)(ust + 4 * (size_t)s * 128);
     perm = (int*)(pslot + 16);
     misc = perm + 128;
   }

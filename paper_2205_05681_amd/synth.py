@@ -511,9 +511,19 @@ def mech_n63(seed=111):
                               must_have=CH4_MUST)
 
 
+def mech_n127(seed=119):
+    """127 species (C, H, O, N; at most C4), 880 reactions: 66 third-body, 44 Troe,
+    with the fuel core (state size 128: the largest state of the
+    four-wavefront kernels, one row per lane in both halves).  The seed is one
+    whose mixtures react within 1e-5 s (up to ~100 steps); several nearby
+    draws take a single step there."""
+    return generate_mechanism(127, 880, 66, 44, True, ["C", "H", "O", "N"], 4, seed,
+                              must_have=CH4_MUST, core=FUEL_CORE)
+
+
 MECHS = {"small": mech_small, "ch4": mech_ch4, "large": mech_large,
          "n15": mech_n15, "n30": mech_n30, "n45": mech_n45, "n55": mech_n55,
-         "n62": mech_n62, "n63": mech_n63}
+         "n62": mech_n62, "n63": mech_n63, "n127": mech_n127}
 
 
 def mechanism_file(name, directory):

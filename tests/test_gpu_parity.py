@@ -322,6 +322,53 @@ def test_mechanism_sizes_team_parity(chem, mech_dir, name):
         assert g[:, c] @ v == pytest.approx(dT, rel=1e-6, abs=1e-9 * np.abs(g[:, c]).sum() + 1e-300), c
 
 
+def test_largest_four_wavefront_state(chem, mech_dir):
+    """127 species (N = 128, the largest state of the four-wavefront kernels;
+    with ROS4's four stages the work-group takes 162,672 of a CU's 163,840
+    bytes of LDS): 48 mixing-layer cells (dt = 1e-5 s, up to ~100 steps) in
+    both team launches against the oracle.  RODAS4's six stages do not fit, so the team modes run it one cell
+    per thread (bit-identical to the plain launch) and the no-allocation entry
+    point refuses it."""
+    import ctypes as C
+    path, m = synth.mechanism_file("n127", mech_dir)
+    o = oracle.Oracle(path)
+    say("case: n127 mechanism (N = 128), 48 cells")
+    T, P, Y = synth.states_mixing(m, 4096, 210)
+    idx = np.r_[np.argsort(-T)[:8], np.arange(40)]
+    T, P, Y = T[idx], P[idx], np.ascontiguousarray(Y[:, idx])
+    mech = chem.Mechanism(path)
+    res = {}
+    for mode in ("team", "team_persistent"):
+        res[mode] = run_gpu(chem, mech, T, P, Y, 1e-5, mode=mode)
+        assert np.all(res[mode][4] == 0)
+    for k in range(5):
+        assert np.array_equal(res["team"][k], res["team_persistent"][k])
+    Tg, Yg, hg, ng, sg = res["team"]
+    say(parity.check_batch(o, T, P, Y, 1e-5, Tg, Yg, ng, "n127 team")[1])
+    a = run_gpu(chem, mech, T, P, Y, 1e-5, mode="team", method="rodas4")
+    b = run_gpu(chem, mech, T, P, Y, 1e-5, mode="plain", method="rodas4")
+    for k in range(5):
+        assert np.array_equal(a[k], b[k])
+    L = chem.lib()
+    L.chem_integrate_noalloc.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                         C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(chem.Opts), C.c_void_p]
+    Tt, Pt, Yt = dev(T), dev(P), dev(Y)
+    T1, Y1 = torch.empty_like(Tt), torch.empty_like(Yt)
+    n = T.size
+    h1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ns = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    vp = lambda t: C.c_void_p(t.data_ptr())
+    opts = chem.default_opts(mode="team", method="rodas4")
+    rc = L.chem_integrate_noalloc(mech.handle, n, vp(Tt), vp(Pt), vp(Yt), n, vp(T1), vp(Y1), 1e-6, 1e-6, 1e-10,
+                                  vp(h1), vp(ns), vp(st), None, C.byref(opts),
+                                  C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == chem.EUNSUPPORTED
+    torch.cuda.synchronize()
+    mech.close()
+
+
 @pytest.fixture(scope="module")
 def large_cells(large):
     """512 of the 111-species mechanism's mixing-layer states (dt = 1e-5 s):

@@ -305,3 +305,61 @@ def test_lu_solve_matches_lapack():
         assert r <= 50 * n * np.finfo(float).eps * np.abs(A).max() * np.abs(x).max()
     with pytest.raises(np.linalg.LinAlgError):
         oracle.lu_solve(np.zeros((3, 3)), np.ones(3))
+
+
+def _lapack_perm(piv):
+    """LAPACK's swap sequence (getrf's ipiv, 0-based) as the row of M taken at each step."""
+    p = np.arange(piv.size)
+    for k, s in enumerate(piv):
+        p[k], p[s] = p[s], p[k]
+    return p
+
+
+def test_lu_factors_match_lapack_getrf():
+    """The factors and pivot order of the stage-matrix LU (a6): LAPACK's
+    getrf (scipy) makes the same choice - the largest magnitude in the column,
+    the first in the current row order on a tie - so on random matrices
+    (with and without forced interchanges and exact ties in the first column)
+    the permutation agrees exactly and the factors to rounding; P M = L U to
+    the backward-error bound, and every multiplier has magnitude <= 1."""
+    import scipy.linalg as sl
+    rng = np.random.default_rng(21)
+    eps = np.finfo(float).eps
+    for n in (1, 2, 5, 16, 54, 112, 128):
+        for case in range(3):
+            M = rng.normal(size=(n, n))
+            if case == 1 and n > 1:
+                M[0, 0] = 0.0                            # forces an interchange
+            if case == 2 and n > 3:
+                M[1, 0], M[3, 0] = 7.0, -7.0             # an exact tie in column 0
+            F, perm, status, margin = oracle.lu(M)
+            assert status == 0
+            lu_ref, piv = sl.lu_factor(M)
+            assert np.array_equal(perm, _lapack_perm(piv))
+            L = np.tril(F, -1) + np.eye(n)
+            U = np.triu(F)
+            assert np.abs(L).max() <= 1.0
+            absLU = np.abs(L) @ np.abs(U)
+            assert np.all(np.abs(L @ U - M[perm]) <= 4 * n * eps * absLU + 1e-300)
+            assert np.all(np.abs(F - lu_ref) <= 4 * n * eps * (absLU / np.maximum(1.0, np.abs(np.diag(U)))[None, :]
+                                                                 + absLU) + 1e-300)
+            if case == 2 and n > 3:
+                assert perm[0] == 1 and margin == 0.0    # the tie goes to the lower row
+            elif n > 1:
+                assert margin > 0.0
+
+
+def test_lu_status_codes():
+    """A zero column gives 1, a column with NaN or an infinity gives 2 (the
+    first failure in column order); a rank-deficient matrix - two equal rows -
+    gives 1 at the step where the repeated row is exhausted."""
+    rng = np.random.default_rng(22)
+    M = rng.normal(size=(6, 6))
+    Z = M.copy(); Z[:, 2] = 0.0
+    assert oracle.lu(Z)[2] == 1
+    N = M.copy(); N[4, 3] = np.nan
+    assert oracle.lu(N)[2] == 2
+    I = M.copy(); I[5, 0] = np.inf
+    assert oracle.lu(I)[2] == 2
+    R = M.copy(); R[3] = R[1]
+    assert oracle.lu(R)[2] == 1
