@@ -599,18 +599,23 @@ __device__ __forceinline__ int team_lu_reg(const double* __restrict__ J, int ldj
 template <int NMAX>
 __device__ __forceinline__ double team_solve_reg(const RegLU<NMAX>& F, int N, double b) {
   const int lane = threadIdx.x;
+  // the L/U selections are made here, in each solve: hoisted out of the
+  // stage loop they became two masked copies of the factors (2 NMAX more
+  // registers, spilled)
+  int ord = F.ord;
+  asm volatile("" : "+v"(ord));
 #pragma unroll
   for (int k = 0; k < NMAX - 1; ++k) {
     const int p = __builtin_amdgcn_readlane(F.pv, k);
     const double yk = bcast(b, p);
-    const double l = (F.ord > k) ? F.A[k] : 0.0;
+    const double l = (ord > k) ? F.A[k] : 0.0;
     b -= l * yk;
   }
 #pragma unroll
   for (int k = NMAX - 1; k > 0; --k) {
     const int p = __builtin_amdgcn_readlane(F.pv, k);
     const double xk = bcast(b, p) * bcast(F.rdg, k);
-    const double u = (F.ord < k) ? F.A[k] : 0.0;
+    const double u = (ord < k) ? F.A[k] : 0.0;
     b -= u * xk;
   }
   const double x = gather(b * F.rown, F.pv);
