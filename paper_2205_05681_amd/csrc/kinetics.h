@@ -262,28 +262,32 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, const Rx
     }
   }
   // sums over the sides (reactants, then products, in slot order) and the
-  // mass-action products; an unused slot contributes nothing
+  // mass-action products; an unused slot contributes nothing.  Branch-free:
+  // an unused slot's coefficient is 0 and its factor 1 (its species is a
+  // valid one, so the terms it adds are exact zeros), and each power is
+  // selected from C, C^2 and C^3 - per-lane branches here cost more than the
+  // arithmetic they skip
   S sg = sc<S>(0.0), sh = sc<S>(0.0);
   S rf = sc<S>(1.0), rr = sc<S>(1.0);
 #pragma unroll
   for (int i = 0; i < MAX_SIDE; ++i) {
-    if (i < nr) {
-      const double v = nuv[i];
-      sg -= v * gq[i];
-      if (want_deriv) sh -= v * hq[i];
-      const S cs = cq[i];
-      rf *= (nuv[i] == 1) ? cs : (nuv[i] == 2 ? cs * cs : cs * cs * cs);
-    }
+    const bool on = i < nr;
+    const double v = on ? (double)nuv[i] : 0.0;
+    sg -= v * gq[i];
+    if (want_deriv) sh -= v * hq[i];
+    const S cs = cq[i], c2 = cs * cs, c3 = c2 * cs;
+    const S pw = (nuv[i] == 1) ? cs : (nuv[i] == 2 ? c2 : c3);
+    rf = on ? rf * pw : rf;
   }
 #pragma unroll
   for (int i = 0; i < MAX_SIDE; ++i) {
-    if (i < np) {
-      const double v = nuv[3 + i];
-      sg += v * gq[3 + i];
-      if (want_deriv) sh += v * hq[3 + i];
-      const S cs = cq[3 + i];
-      rr *= (nuv[3 + i] == 1) ? cs : (nuv[3 + i] == 2 ? cs * cs : cs * cs * cs);
-    }
+    const bool on = i < np;
+    const double v = on ? (double)nuv[3 + i] : 0.0;
+    sg += v * gq[3 + i];
+    if (want_deriv) sh += v * hq[3 + i];
+    const S cs = cq[3 + i], c2 = cs * cs, c3 = c2 * cs;
+    const S pw = (nuv[3 + i] == 1) ? cs : (nuv[3 + i] == 2 ? c2 : c3);
+    rr = on ? rr * pw : rr;
   }
   const S lnKc = sg + dnu * log(PATM / (RU * T));
   const S kr = k * exp(-lnKc);

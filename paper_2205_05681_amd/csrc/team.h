@@ -210,11 +210,14 @@ __device__ __forceinline__ double team_rhs(const MechView& M, double P, double y
     nx = load_rxn(M, j + 64 < Nr ? j + 64 : j, lnA);
     const RateOut r = reaction_rate(M, R, T, lnT, iT, ctot, Lane{conc.p, 1}, Lane{gib.p, 1},
                                     Lane{hrt.p, 1}, false);
-    // slots with compile-time bounds (unused slots hold 0)
+    // slots with compile-time bounds: an unused slot adds to this lane's own
+    // dummy cell (dwdT is used only by the Jacobian), so no per-lane branch
+    double* const dummy = L.dwdT + lane;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       const int sq = R.sp[q], nq = R.nu[q];
-      if ((q < 3) ? (q < R.nr) : (q - 3 < R.np)) atomicAdd(&L.wdot[sq], (q < 3 ? -nq : nq) * r.q);
+      const bool on = (q < 3) ? (q < R.nr) : (q - 3 < R.np);
+      atomicAdd(on ? &L.wdot[sq] : dummy, (q < 3 ? -nq : nq) * r.q);
     }
   }
   wsync();

@@ -198,11 +198,14 @@ __device__ __forceinline__ V2 t4_rhs(const MechView& M, double P, const V2& y, T
     const RateOut r = reaction_rate(M, R, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
                                     Lane{L.hrt, 1}, false);
     for (int ph = 0; ph < 4; ++ph) {
-      if (w == ph && have) {
+      if (w == ph) {
+        // an unused slot, or a thread past the last reaction, adds to the
+        // thread's own dummy cell: no per-lane branch
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
           const int sq = R.sp[q], nq = R.nu[q];
-          if ((q < 3) ? (q < R.nr) : (q - 3 < R.np)) atomicAdd(&L.wdot[sq], (q < 3 ? -nq : nq) * r.q);
+          const bool on = have && ((q < 3) ? (q < R.nr) : (q - 3 < R.np));
+          atomicAdd(on ? &L.wdot[sq] : L.dummy + tid, (q < 3 ? -nq : nq) * r.q);
         }
       }
       wsync();
