@@ -175,7 +175,10 @@ __device__ __forceinline__ RxnRec load_rxn(const MechView& M, int j, const doubl
   return r;
 }
 
-template <class S>
+// SIDE < MAX_SIDE: every reaction of the call has at most SIDE species on
+// each side, and slots past SIDE are neither read nor used (the caller checks
+// this for the whole wavefront; the result is the same as with MAX_SIDE).
+template <class S, int SIDE = MAX_SIDE>
 __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, const RxnRec& R, S T, S lnT, S iT,
                                                      S ctot, LaneT<S> conc, LaneT<S> gib,
                                                      LaneT<S> hrt, bool want_deriv) {
@@ -190,9 +193,10 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, const Rx
   S cq[6], gq[6], hq[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    cq[q] = conc[spv[q]];
-    gq[q] = gib[spv[q]];
-    hq[q] = want_deriv ? hrt[spv[q]] : sc<S>(0.0);
+    const bool used = (q % 3) < SIDE;
+    cq[q] = used ? conc[spv[q]] : sc<S>(0.0);
+    gq[q] = used ? gib[spv[q]] : sc<S>(0.0);
+    hq[q] = (used && want_deriv) ? hrt[spv[q]] : sc<S>(0.0);
   }
   const S lnkinf = lnA + b * lnT - th * iT;
   const S kinf = exp(lnkinf);
@@ -270,7 +274,7 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, const Rx
   S sg = sc<S>(0.0), sh = sc<S>(0.0);
   S rf = sc<S>(1.0), rr = sc<S>(1.0);
 #pragma unroll
-  for (int i = 0; i < MAX_SIDE; ++i) {
+  for (int i = 0; i < SIDE; ++i) {
     const bool on = i < nr;
     const double v = on ? (double)nuv[i] : 0.0;
     sg -= v * gq[i];
@@ -280,7 +284,7 @@ __device__ __forceinline__ RateOutT<S> reaction_rate(const MechView& M, const Rx
     rf = on ? rf * pw : rf;
   }
 #pragma unroll
-  for (int i = 0; i < MAX_SIDE; ++i) {
+  for (int i = 0; i < SIDE; ++i) {
     const bool on = i < np;
     const double v = on ? (double)nuv[3 + i] : 0.0;
     sg += v * gq[3 + i];

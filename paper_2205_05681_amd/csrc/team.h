@@ -191,6 +191,24 @@ __device__ __forceinline__ void team_state(const MechView& M, double P, S y, Tea
   wsync();
 }
 
+// One reaction of the f loop: its rate and its scatter into wdot, slots up to
+// SIDE per side.  An unused slot adds to this lane's own dummy cell (dwdT is
+// used only by the Jacobian), so no per-lane branch.
+template <int SIDE>
+__device__ __forceinline__ void team_rhs_reaction(const MechView& M, const RxnRec& R, double T, double lnT,
+                                                  double iT, double ctot, TeamLds& L) {
+  const RateOut r = reaction_rate<double, SIDE>(M, R, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
+                                                Lane{L.hrt, 1}, false);
+  double* const dummy = L.dwdT + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q % 3 >= SIDE) continue;
+    const int sq = R.sp[q], nq = R.nu[q];
+    const bool on = (q < 3) ? (q < R.nr) : (q - 3 < R.np);
+    atomicAdd(on ? &L.wdot[sq] : dummy, (q < 3 ? -nq : nq) * r.q);
+  }
+}
+
 // f(y) for lane-distributed y; returns f_i in lane i.
 __device__ __forceinline__ double team_rhs(const MechView& M, double P, double y, TeamLds& L,
                            const double* __restrict__ lnA) {
@@ -201,24 +219,18 @@ __device__ __forceinline__ double team_rhs(const MechView& M, double P, double y
   if (lane < K) L.wdot[lane] = 0.0;
   wsync();
   const double lnT = log(T), iT = 1.0 / T;
-  LdsLane conc{L.conc}, gib{L.gib}, hrt{L.hrt};
   // the next reaction's record is fetched while this one is worked on
   const int Nr = M.Nr;
   RxnRec nx = load_rxn(M, lane < Nr ? lane : Nr - 1, lnA);
   for (int j = lane; j < Nr; j += 64) {
     const RxnRec R = nx;
     nx = load_rxn(M, j + 64 < Nr ? j + 64 : j, lnA);
-    const RateOut r = reaction_rate(M, R, T, lnT, iT, ctot, Lane{conc.p, 1}, Lane{gib.p, 1},
-                                    Lane{hrt.p, 1}, false);
-    // slots with compile-time bounds: an unused slot adds to this lane's own
-    // dummy cell (dwdT is used only by the Jacobian), so no per-lane branch
-    double* const dummy = L.dwdT + lane;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int sq = R.sp[q], nq = R.nu[q];
-      const bool on = (q < 3) ? (q < R.nr) : (q - 3 < R.np);
-      atomicAdd(on ? &L.wdot[sq] : dummy, (q < 3 ? -nq : nq) * r.q);
-    }
+    // most passes hold two-by-two reactions only: then the third slot of each
+    // side is left out (a wave-uniform choice, once per pass)
+    if (__all(R.nr <= 2 && R.np <= 2))
+      team_rhs_reaction<2>(M, R, T, lnT, iT, ctot, L);
+    else
+      team_rhs_reaction<MAX_SIDE>(M, R, T, lnT, iT, ctot, L);
   }
   wsync();
   double w = 0.0, num = 0.0, den = 0.0;
@@ -237,6 +249,99 @@ __device__ __forceinline__ double team_rhs(const MechView& M, double P, double y
   if (lane >= 2 && lane < N) f = V * L.wdot[lane - 2];
   wsync();
   return f;
+}
+
+// One reaction of the Jacobian loop: its rate with derivatives, d q / d(T, C)
+// and the scatter into the rows of G, slots up to SIDE per side.  Unused
+// slots send their updates to this lane's own dummy cell (dwdT is written
+// only after the reaction loop).
+template <class S, int SIDE>
+__device__ __forceinline__ void team_jac_reaction(const MechView& M, const RxnRec& R, S T, S lnT, S iT,
+                                                  S ctot, TeamLdsT<S>& L, int K, int ldj) {
+  const RateOutT<S> r = reaction_rate<S, SIDE>(M, R, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
+                                               LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, true);
+  const int nr = R.nr, np = R.np;
+  const S dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
+  // participant slots 0..2 (reactants) and 3..5 (products), with compile-time
+  // bounds: an unused slot has coefficient 0, and its updates go to this
+  // lane's own dummy cell (dwdT is written only after this loop)
+  S* const dummy = L.dwdT + threadIdx.x;
+  int ks[6], nus[6];
+  bool on[6];
+  S cs[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    on[q] = (q % 3 < SIDE) && ((q < 3) ? (q < nr) : (q - 3 < np));
+    ks[q] = R.sp[q];         // unused slots hold species 0 and coefficient 0
+    nus[q] = R.nu[q];
+    cs[q] = (q % 3 < SIDE) ? L.conc[ks[q]] : sc<S>(0.0);
+  }
+  // d q / d C of slot q: the mass-action product of its side with the power
+  // of C_q lowered by one (the same multiplications, in the same order, as a
+  // loop over the side's species)
+  S dq[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int s0 = q < 3 ? 0 : 3;
+    S d = (q < 3) ? r.kf : r.kr;
+#pragma unroll
+    for (int l = 0; l < SIDE; ++l) {
+      const int v = (s0 + l == q) ? nus[s0 + l] - 1 : nus[s0 + l];
+      const S c = cs[s0 + l];
+      d = (v >= 1) ? d * c : d;
+      d = (v >= 2) ? d * c : d;
+      d = (v >= 3) ? d * c : d;
+    }
+    dq[q] = d * (double)(q < 3 ? nus[q] : -nus[q]);
+  }
+  // scatter into row k = ks[q] of G (T column, species columns, bath column)
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q % 3 >= SIDE) continue;
+    const int k = ks[q];
+    const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
+    S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+    lds_add(on[q] ? &L.wdot[k] : dummy, vk * r.q);
+    lds_add(on[q] ? &row[0] : dummy, vk * dqdT);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      if (t % 3 >= SIDE) continue;
+      const int m = ks[t];
+      S* dst = (m == K - 1) ? &L.gb[k] : &row[m + 2];
+      lds_add((on[q] && on[t]) ? dst : dummy, vk * dq[t]);
+    }
+  }
+  if (R.type != RX_ELEM) {
+    // third body and falloff: the uniform [M] part and the efficiency
+    // columns; the first four efficiencies are read together up front, any
+    // further ones in a loop
+    const int e0 = R.e0, e1 = R.e1;
+    int em[4];
+    double ea[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = (e0 + t < e1) ? e0 + t : e0;   // in the table, or its padding when e0 == e1
+      em[t] = M.eff_idx[e];
+      ea[t] = M.eff_am1[e];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      if (q % 3 >= SIDE) continue;
+      const int k = ks[q];
+      const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
+      S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+      lds_add(on[q] ? &L.tb[k] : dummy, vk * r.beta);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        S* dst = (em[t] == K - 1) ? &L.gb[k] : &row[em[t] + 2];
+        lds_add((on[q] && e0 + t < e1) ? dst : dummy, (vk * ea[t]) * r.beta);
+      }
+      for (int e = e0 + 4; e < e1; ++e) {
+        const int m = M.eff_idx[e];
+        lds_add(on[q] ? ((m == K - 1) ? &L.gb[k] : &row[m + 2]) : dummy, (vk * M.eff_am1[e]) * r.beta);
+      }
+    }
+  }
 }
 
 // f(y) and the Jacobian, assembled in L.J (row i at L.J[i*(N+1)]).  S is
@@ -265,87 +370,12 @@ __device__ __forceinline__ S team_rhs_jac(const MechView& M, double P, S y, Team
   for (int j = lane; j < Nr; j += 64) {
     const RxnRec R = nx;
     nx = load_rxn(M, j + 64 < Nr ? j + 64 : j, lnA);
-    const RateOutT<S> r = reaction_rate(M, R, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
-                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, true);
-    const int nr = R.nr, np = R.np;
-    const S dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
-    // participant slots 0..2 (reactants) and 3..5 (products), with compile-time
-    // bounds: an unused slot has coefficient 0, and its updates go to this
-    // lane's own dummy cell (dwdT is written only after this loop)
-    S* const dummy = L.dwdT + lane;
-    int ks[6], nus[6];
-    bool on[6];
-    S cs[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      on[q] = (q < 3) ? (q < nr) : (q - 3 < np);
-      ks[q] = R.sp[q];         // unused slots hold species 0 and coefficient 0
-      nus[q] = R.nu[q];
-      cs[q] = L.conc[ks[q]];
-    }
-    // d q / d C of slot q: the mass-action product of its side with the power
-    // of C_q lowered by one (the same multiplications, in the same order, as a
-    // loop over the side's species)
-    S dq[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int s0 = q < 3 ? 0 : 3;
-      S d = (q < 3) ? r.kf : r.kr;
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        const int v = (s0 + l == q) ? nus[s0 + l] - 1 : nus[s0 + l];
-        const S c = cs[s0 + l];
-        d = (v >= 1) ? d * c : d;
-        d = (v >= 2) ? d * c : d;
-        d = (v >= 3) ? d * c : d;
-      }
-      dq[q] = d * (double)(q < 3 ? nus[q] : -nus[q]);
-    }
-    // scatter into row k = ks[q] of G (T column, species columns, bath column)
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int k = ks[q];
-      const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
-      S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-      lds_add(on[q] ? &L.wdot[k] : dummy, vk * r.q);
-      lds_add(on[q] ? &row[0] : dummy, vk * dqdT);
-#pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        const int m = ks[t];
-        S* dst = (m == K - 1) ? &L.gb[k] : &row[m + 2];
-        lds_add((on[q] && on[t]) ? dst : dummy, vk * dq[t]);
-      }
-    }
-    if (R.type != RX_ELEM) {
-      // third body and falloff: the uniform [M] part and the efficiency
-      // columns; the first four efficiencies are read together up front, any
-      // further ones in a loop
-      const int e0 = R.e0, e1 = R.e1;
-      int em[4];
-      double ea[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int e = (e0 + t < e1) ? e0 + t : e0;   // in the table, or its padding when e0 == e1
-        em[t] = M.eff_idx[e];
-        ea[t] = M.eff_am1[e];
-      }
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const int k = ks[q];
-        const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
-        S* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-        lds_add(on[q] ? &L.tb[k] : dummy, vk * r.beta);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          S* dst = (em[t] == K - 1) ? &L.gb[k] : &row[em[t] + 2];
-          lds_add((on[q] && e0 + t < e1) ? dst : dummy, (vk * ea[t]) * r.beta);
-        }
-        for (int e = e0 + 4; e < e1; ++e) {
-          const int m = M.eff_idx[e];
-          lds_add(on[q] ? ((m == K - 1) ? &L.gb[k] : &row[m + 2]) : dummy, (vk * M.eff_am1[e]) * r.beta);
-        }
-      }
-    }
+    // most passes hold two-by-two reactions only: then the third slot of each
+    // side is left out (a wave-uniform choice, once per pass)
+    if (__all(R.nr <= 2 && R.np <= 2))
+      team_jac_reaction<S, 2>(M, R, T, lnT, iT, ctot, L, K, ldj);
+    else
+      team_jac_reaction<S, MAX_SIDE>(M, R, T, lnT, iT, ctot, L, K, ldj);
   }
   wsync();
   // pass 1, row-parallel (lane k = species row): Phi coordinates of row k
