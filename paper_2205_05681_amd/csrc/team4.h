@@ -174,6 +174,20 @@ __device__ __forceinline__ V2 t4_pack_f(int N, double Tdot, double Vdot, double 
   return f;
 }
 
+// The f scatter of one reaction, slots up to SIDE per side: an unused slot,
+// or a thread past the last reaction, adds to the thread's own dummy cell (no
+// per-lane branch).
+template <int SIDE>
+__device__ __forceinline__ void t4_rhs_scatter(const RxnRec& R, double q_rate, bool have, Team4Lds& L, int tid) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q % 3 >= SIDE) continue;
+    const int sq = R.sp[q], nq = R.nu[q];
+    const bool on = have && ((q < 3) ? (q < R.nr) : (q - 3 < R.np));
+    atomicAdd(on ? &L.wdot[sq] : L.dummy + tid, (q < 3 ? -nq : nq) * q_rate);
+  }
+}
+
 // f(y).
 __device__ __forceinline__ V2 t4_rhs(const MechView& M, double P, const V2& y, Team4Lds& L,
                                      const double* __restrict__ lnA) {
@@ -195,18 +209,19 @@ __device__ __forceinline__ V2 t4_rhs(const MechView& M, double P, const V2& y, T
     const bool have = j < Nr;
     const RxnRec R = nx;
     nx = load_rxn(M, j + T4_THREADS < Nr ? j + T4_THREADS : 0, lnA);
-    const RateOut r = reaction_rate(M, R, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
-                                    Lane{L.hrt, 1}, false);
+    // a wavefront whose reactions all have two species a side leaves the
+    // third slots out (a wave-uniform choice)
+    const bool two = __all(R.nr <= 2 && R.np <= 2);
+    const RateOut r = two ? reaction_rate<double, 2>(M, R, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
+                                                     Lane{L.hrt, 1}, false)
+                          : reaction_rate<double, MAX_SIDE>(M, R, T, lnT, iT, ctot, Lane{L.conc, 1},
+                                                            Lane{L.gib, 1}, Lane{L.hrt, 1}, false);
     for (int ph = 0; ph < 4; ++ph) {
       if (w == ph) {
-        // an unused slot, or a thread past the last reaction, adds to the
-        // thread's own dummy cell: no per-lane branch
-#pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          const int sq = R.sp[q], nq = R.nu[q];
-          const bool on = have && ((q < 3) ? (q < R.nr) : (q - 3 < R.np));
-          atomicAdd(on ? &L.wdot[sq] : L.dummy + tid, (q < 3 ? -nq : nq) * r.q);
-        }
+        if (two)
+          t4_rhs_scatter<2>(R, r.q, have, L, tid);
+        else
+          t4_rhs_scatter<MAX_SIDE>(R, r.q, have, L, tid);
       }
       wsync();
     }
@@ -223,6 +238,63 @@ __device__ __forceinline__ V2 t4_rhs(const MechView& M, double P, const V2& y, T
   const V2 f = t4_pack_f(N, Tdot, V * (Tdot * iT + (RU * T / P) * r3[2]), V, L.wdot);
   wsync();
   return f;
+}
+
+// The Jacobian scatter of one reaction into the rows of G, slots up to SIDE
+// per side; an unused slot, or a thread past the last reaction, sends its
+// updates to the thread's own dummy cell.
+template <int SIDE>
+__device__ __forceinline__ void t4_jac_scatter(const MechView& M, const RxnRec& R, const RateOut& r, double dqdT,
+                                               const int (&ks)[6], const int (&nus)[6], const bool (&on_in)[6],
+                                               const double (&dq)[6], bool have, Team4Lds& L, int K, int ldj,
+                                               double* dummy) {
+  bool on[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) on[q] = have && on_in[q];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q % 3 >= SIDE) continue;
+    const int k = ks[q];
+    const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
+    double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+    lds_add(on[q] ? &L.wdot[k] : dummy, vk * r.q);
+    lds_add(on[q] ? &row[0] : dummy, vk * dqdT);
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      if (t % 3 >= SIDE) continue;
+      const int mm = ks[t];
+      double* dst = (mm == K - 1) ? &L.gb[k] : &row[mm + 2];
+      lds_add((on[q] && on[t]) ? dst : dummy, vk * dq[t]);
+    }
+  }
+  if (R.type != RX_ELEM) {
+    const int e0 = R.e0, e1 = R.e1;
+    int em[4];
+    double ea[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = (e0 + t < e1) ? e0 + t : e0;
+      em[t] = M.eff_idx[e];
+      ea[t] = M.eff_am1[e];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      if (q % 3 >= SIDE) continue;
+      const int k = ks[q];
+      const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
+      double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
+      lds_add(on[q] ? &L.tb[k] : dummy, vk * r.beta);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        double* dst = (em[t] == K - 1) ? &L.gb[k] : &row[em[t] + 2];
+        lds_add((on[q] && e0 + t < e1) ? dst : dummy, (vk * ea[t]) * r.beta);
+      }
+      for (int e = e0 + 4; e < e1; ++e) {
+        const int mm = M.eff_idx[e];
+        lds_add(on[q] ? ((mm == K - 1) ? &L.gb[k] : &row[mm + 2]) : dummy, (vk * M.eff_am1[e]) * r.beta);
+      }
+    }
+  }
 }
 
 // f(y) and the Jacobian, assembled in L.J (row i at L.J[i*(N+1)]).  The same
@@ -255,8 +327,13 @@ __device__ __forceinline__ V2 t4_rhs_jac(const MechView& M, double P, const V2& 
     const bool have = j < Nr;
     const RxnRec R = nx;
     nx = load_rxn(M, j + T4_THREADS < Nr ? j + T4_THREADS : 0, lnA);
-    const RateOut r = reaction_rate(M, R, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
-                                    Lane{L.hrt, 1}, true);
+    // a wavefront whose reactions all have two species a side leaves the
+    // third slots out (a wave-uniform choice)
+    const bool two = __all(R.nr <= 2 && R.np <= 2);
+    const RateOut r = two ? reaction_rate<double, 2>(M, R, T, lnT, iT, ctot, Lane{L.conc, 1}, Lane{L.gib, 1},
+                                                     Lane{L.hrt, 1}, true)
+                          : reaction_rate<double, MAX_SIDE>(M, R, T, lnT, iT, ctot, Lane{L.conc, 1},
+                                                            Lane{L.gib, 1}, Lane{L.hrt, 1}, true);
     const int nr = R.nr, np = R.np;
     const double dqdT = r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT;
     double* const dummy = L.dummy + tid;
@@ -286,50 +363,13 @@ __device__ __forceinline__ V2 t4_rhs_jac(const MechView& M, double P, const V2& 
       dq[q] = d * (double)(q < 3 ? nus[q] : -nus[q]);
     }
     for (int ph = 0; ph < 4; ++ph) {
-    if (w == ph && have) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int k = ks[q];
-      const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
-      double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-      lds_add(on[q] ? &L.wdot[k] : dummy, vk * r.q);
-      lds_add(on[q] ? &row[0] : dummy, vk * dqdT);
-#pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        const int mm = ks[t];
-        double* dst = (mm == K - 1) ? &L.gb[k] : &row[mm + 2];
-        lds_add((on[q] && on[t]) ? dst : dummy, vk * dq[t]);
+      if (w == ph) {
+        if (two)
+          t4_jac_scatter<2>(M, R, r, dqdT, ks, nus, on, dq, have, L, K, ldj, dummy);
+        else
+          t4_jac_scatter<MAX_SIDE>(M, R, r, dqdT, ks, nus, on, dq, have, L, K, ldj, dummy);
       }
-    }
-    if (R.type != RX_ELEM) {
-      const int e0 = R.e0, e1 = R.e1;
-      int em[4];
-      double ea[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int e = (e0 + t < e1) ? e0 + t : e0;
-        em[t] = M.eff_idx[e];
-        ea[t] = M.eff_am1[e];
-      }
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const int k = ks[q];
-        const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
-        double* row = (k == K - 1) ? L.brow : L.J + (k + 2) * ldj;
-        lds_add(on[q] ? &L.tb[k] : dummy, vk * r.beta);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          double* dst = (em[t] == K - 1) ? &L.gb[k] : &row[em[t] + 2];
-          lds_add((on[q] && e0 + t < e1) ? dst : dummy, (vk * ea[t]) * r.beta);
-        }
-        for (int e = e0 + 4; e < e1; ++e) {
-          const int mm = M.eff_idx[e];
-          lds_add(on[q] ? ((mm == K - 1) ? &L.gb[k] : &row[mm + 2]) : dummy, (vk * M.eff_am1[e]) * r.beta);
-        }
-      }
-    }
-    }
-    wsync();
+      wsync();
     }
   }
   // pass 1, species row k on thread k
