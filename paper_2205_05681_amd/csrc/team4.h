@@ -12,13 +12,16 @@
 //     FP64 LDS atomics, column c on thread c (the T and V rows); sums over
 //     species are wave sums combined through LDS in a fixed order;
 //   * the LU of M = I/(h gamma) - J is split over the wavefronts by columns
-//     of the matrix padded to 128 x 128 with identity rows and columns: wave w
-//     holds columns 32 w .. 32 w + 31 of every row, rows lane and 64 + lane in
-//     64 registers per lane.  At column k the wavefront holding it alone finds
-//     the largest |a| over the unused rows (exact, ties to the lowest row) and
-//     the multipliers and puts them in LDS; after one work-group barrier every
-//     wavefront updates its columns right of k, reading the pivot row's
-//     entries from its own registers (v_readlane);
+//     of the matrix padded to 128 x 128 with identity rows and columns, dealt
+//     round-robin: wave w holds columns 4 j + w (j < 32) of every row, rows
+//     lane and 64 + lane in 64 registers per lane, so the columns right of
+//     any k are spread evenly over the four.  At column k the wavefront
+//     holding it alone finds the largest |a| over the unused rows (exact, ties
+//     to the lowest row) and the multipliers and puts them in LDS; after one
+//     work-group barrier every wavefront updates its columns right of k,
+//     reading the pivot row's entries from its own registers (v_readlane);
+//     the wavefront holding column k + 1 updates that column first and
+//     searches its pivot before the rest of its update;
 //   * the triangular solves run in every wavefront on its own copy of the
 //     vector (no barrier), reading the factors from LDS.
 #pragma once
@@ -447,78 +450,93 @@ __device__ __forceinline__ V2 t4_rhs_jac(const MechView& M, double P, const V2& 
   return f;
 }
 
-// Column-block LU: wave w holds columns 32 w + jj (jj < 32) of rows lane and
+// Column-cyclic LU: wave w holds column 4 jj + w (jj < 32) of rows lane and
 // 64 + lane in A0[jj], A1[jj] (the matrix padded to 128 x 128 with identity
-// rows and columns).  At column KC the wavefront owning it alone finds the
-// pivot (exact largest |a| over the unused rows, ties to the lowest row) and
-// the multipliers, and publishes the pivot row index and the multipliers in
-// LDS (two buffers, alternating with the column parity); after one
-// work-group barrier every wavefront updates its columns right of KC, taking
-// the pivot row's entries from its own registers by v_readlane.
+// rows and columns).  At column KC the wavefront owning it (KC % 4, local
+// index KC / 4) alone finds the pivot (exact largest |a| over the unused rows,
+// ties to the lowest row) and the multipliers, and publishes the pivot row
+// index and the multipliers in LDS (two buffers, alternating with the column
+// parity); after one work-group barrier every wavefront updates its columns
+// right of KC, taking the pivot row's entries from its own registers by
+// v_readlane.  The search for column KC + 1 runs in step KC, by its wavefront,
+// right after that column's update and before its other columns.
 
-// Rows lane, 64 + lane: A -= l u over the local columns J0..31, u the pivot
-// row (lane pl, second half when ph).
-template <int J0>
+// Rows lane, 64 + lane: A -= l u over the local columns J0..J1-1, u the
+// pivot row (lane pl, second half when ph).
+template <int J0, int J1 = 32>
 __device__ __forceinline__ void t4c_update(double (&A0)[32], double (&A1)[32], double l0, double l1, int pl,
                                            bool ph) {
 #pragma unroll
-  for (int jj = J0; jj < 32; ++jj) {
+  for (int jj = J0; jj < J1; ++jj) {
     const double u = bcast(ph ? A1[jj] : A0[jj], pl);
     A0[jj] -= l0 * u;
     A1[jj] -= l1 * u;
   }
 }
 
+// Column KC's pivot and multipliers, by the wavefront holding the column
+// (local index KC / 4): the exact largest |a| over the unused rows, ties to
+// the lowest row (its first half, then its second); the multipliers replace
+// the column, and the pivot row, the multipliers, 1 / pivot and the first
+// failure code go to LDS (buffer KC & 1).
 template <int KC>
-__device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team4Lds& L, int& ord0, int& ord1) {
+__device__ __forceinline__ void t4c_search(double (&A0)[32], double (&A1)[32], Team4Lds& L, int ord0, int ord1,
+                                           int& p, double& l0, double& l1) {
+  constexpr int KK = KC / 4;
+  const int lane = t4_lane();
+  double* lc = L.prow + 128 * (KC & 1);   // L.prow and L.lcol: two buffers of 128
+  const bool act0 = ord0 < 0, act1 = ord1 < 0;
+  const double a0 = fabs(A0[KK]), a1 = fabs(A1[KK]);
+  // the IEEE words of a non-negative double order like the value
+  const unsigned h0 = act0 ? (unsigned)__double2hiint(a0) : 0u, w0 = act0 ? (unsigned)__double2loint(a0) : 0u;
+  const unsigned h1 = act1 ? (unsigned)__double2hiint(a1) : 0u, w1 = act1 ? (unsigned)__double2loint(a1) : 0u;
+  const bool t1 = h1 > h0 || (h1 == h0 && w1 > w0);
+  const unsigned bh = t1 ? h1 : h0, bl = t1 ? w1 : w0;
+  const unsigned mhi = wave_max_u32(bh);
+  const bool cand = bh == mhi;
+  unsigned mlo;
+  const unsigned long long sel = __ballot(cand);
+  if (__builtin_popcountll(sel) > 1)   // several lanes share the high word
+    mlo = wave_max_u32(cand ? bl : 0u);
+  else
+    mlo = (unsigned)__builtin_amdgcn_readlane((int)bl, __builtin_amdgcn_readfirstlane(__ffsll(sel) - 1));
+  const unsigned long long s0 = __ballot(act0 && h0 == mhi && w0 == mlo);
+  const unsigned long long s1 = __ballot(act1 && h1 == mhi && w1 == mlo);
+  p = __builtin_amdgcn_readfirstlane(s0 ? __ffsll(s0) - 1 : 64 + __ffsll(s1) - 1);
+  const bool nonfinite = __any((act0 && h0 >= 0x7FF00000u) || (act1 && h1 >= 0x7FF00000u));
+  const int code = nonfinite ? 2 : ((mhi | mlo) == 0u ? 1 : 0);
+  const double piv = bcast(p >= 64 ? A1[KK] : A0[KK], p & 63);
+  const double rp = 1.0 / piv;
+  const bool u0 = act0 && p != lane, u1 = act1 && p != 64 + lane;
+  l0 = u0 ? A0[KK] * rp : 0.0;
+  l1 = u1 ? A1[KK] * rp : 0.0;
+  A0[KK] = u0 ? l0 : A0[KK];
+  A1[KK] = u1 ? l1 : A1[KK];
+  lc[lane] = l0;
+  lc[64 + lane] = l1;
+  if (lane == 0) {
+    L.pslot[KC & 1] = (unsigned)p;
+    L.perm[KC] = p;
+    L.rdg[KC] = rp;
+    if (L.pslot[2] == 0u && code) L.pslot[2] = (unsigned)code;   // the first failure in column order
+  }
+  // keep the column's values here (not sunk past the later columns)
+  asm volatile("" : "+v"(l0), "+v"(l1));
+}
+
+// Elimination step KC.  On entry column KC's pivot and multipliers are in
+// LDS (buffer KC & 1, behind a barrier) and, in the wavefront holding the
+// column, in p, l0, l1.  Wavefront w's columns right of KC are its local
+// columns from KC / 4 on when w > KC % 4, from KC / 4 + 1 otherwise.
+template <int KC>
+__device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team4Lds& L, int& ord0, int& ord1,
+                                        int p, double l0, double l1) {
   if constexpr (KC < T4_NMAX) {
-    constexpr int W = KC / 32, KK = KC % 32;
+    constexpr int W = KC % 4, KK = KC / 4;
+    constexpr int W1 = (KC + 1) % 4, K1 = (KC + 1) / 4;   // the next column's wavefront and local index
     const int w = t4_wave(), lane = t4_lane();
-    double* lc = L.prow + 128 * (KC & 1);   // L.prow and L.lcol: two buffers of 128
-    double l0 = 0.0, l1 = 0.0;
-    int p = 0;
-    if (w == W) {
-      const bool act0 = ord0 < 0, act1 = ord1 < 0;
-      const double a0 = fabs(A0[KK]), a1 = fabs(A1[KK]);
-      // the IEEE words of a non-negative double order like the value
-      const unsigned h0 = act0 ? (unsigned)__double2hiint(a0) : 0u, w0 = act0 ? (unsigned)__double2loint(a0) : 0u;
-      const unsigned h1 = act1 ? (unsigned)__double2hiint(a1) : 0u, w1 = act1 ? (unsigned)__double2loint(a1) : 0u;
-      const bool t1 = h1 > h0 || (h1 == h0 && w1 > w0);
-      const unsigned bh = t1 ? h1 : h0, bl = t1 ? w1 : w0;
-      const unsigned mhi = wave_max_u32(bh);
-      const bool cand = bh == mhi;
-      unsigned mlo;
-      const unsigned long long sel = __ballot(cand);
-      if (__builtin_popcountll(sel) > 1)   // several lanes share the high word
-        mlo = wave_max_u32(cand ? bl : 0u);
-      else
-        mlo = (unsigned)__builtin_amdgcn_readlane((int)bl, __builtin_amdgcn_readfirstlane(__ffsll(sel) - 1));
-      // the lowest row with the largest key: the first half, then the second
-      const unsigned long long s0 = __ballot(act0 && h0 == mhi && w0 == mlo);
-      const unsigned long long s1 = __ballot(act1 && h1 == mhi && w1 == mlo);
-      p = __builtin_amdgcn_readfirstlane(s0 ? __ffsll(s0) - 1 : 64 + __ffsll(s1) - 1);
-      const bool nonfinite = __any((act0 && h0 >= 0x7FF00000u) || (act1 && h1 >= 0x7FF00000u));
-      const int code = nonfinite ? 2 : ((mhi | mlo) == 0u ? 1 : 0);
-      const double piv = bcast(p >= 64 ? A1[KK] : A0[KK], p & 63);
-      const double rp = 1.0 / piv;
-      const bool u0 = act0 && p != lane, u1 = act1 && p != 64 + lane;
-      l0 = u0 ? A0[KK] * rp : 0.0;
-      l1 = u1 ? A1[KK] * rp : 0.0;
-      A0[KK] = u0 ? l0 : A0[KK];
-      A1[KK] = u1 ? l1 : A1[KK];
-      lc[lane] = l0;
-      lc[64 + lane] = l1;
-      if (lane == 0) {
-        L.pslot[KC & 1] = (unsigned)p;
-        L.perm[KC] = p;
-        L.rdg[KC] = rp;
-        if (L.pslot[2] == 0u && code) L.pslot[2] = (unsigned)code;   // the first failure in column order
-      }
-      // keep the column's values here (not sunk past the later columns)
-      asm volatile("" : "+v"(l0), "+v"(l1));
-    }
-    wsync();
     if (w != W) {
+      const double* lc = L.prow + 128 * (KC & 1);
       p = (int)L.pslot[KC & 1];
       l0 = lc[lane];
       l1 = lc[64 + lane];
@@ -528,11 +546,21 @@ __device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team
     asm volatile("" : "+v"(ord0), "+v"(ord1));
     const int pl = p & 63;
     const bool ph = p >= 64;
-    if (w > W)
-      t4c_update<0>(A0, A1, l0, l1, pl, ph);
-    else if (w == W)
-      t4c_update<KK + 1>(A0, A1, l0, l1, pl, ph);
-    t4c_col<KC + 1>(A0, A1, L, ord0, ord1);
+    int pn = 0;
+    double m0 = 0.0, m1 = 0.0;   // column KC + 1's pivot and multipliers (its wavefront)
+    if constexpr (KC + 1 < T4_NMAX) {
+      if (w == W1) {
+        t4c_update<K1, K1 + 1>(A0, A1, l0, l1, pl, ph);
+        t4c_search<KC + 1>(A0, A1, L, ord0, ord1, pn, m0, m1);
+        t4c_update<K1 + 1>(A0, A1, l0, l1, pl, ph);
+      } else if (w > W) {
+        t4c_update<KK>(A0, A1, l0, l1, pl, ph);
+      } else {
+        t4c_update<KK + 1>(A0, A1, l0, l1, pl, ph);
+      }
+      wsync();
+    }
+    t4c_col<KC + 1>(A0, A1, L, ord0, ord1, pn, m0, m1);
   }
 }
 
@@ -549,29 +577,32 @@ __device__ __forceinline__ int t4_lu(double* __restrict__ F, int ldj, int N, dou
   const int w = t4_wave(), lane = t4_lane();
   const int r0 = lane, r1 = 64 + lane;
   const bool own0 = r0 < N, own1 = r1 < N;
-  const double* row0 = F + (own0 ? r0 : 0) * ldj + 32 * w;
-  const double* row1 = F + (own1 ? r1 : 0) * ldj + 32 * w;
-  const int jn0 = own0 ? N - 32 * w : 0, jn1 = own1 ? N - 32 * w : 0;   // entries of M in each row segment
+  const double* row0 = F + (own0 ? r0 : 0) * ldj;
+  const double* row1 = F + (own1 ? r1 : 0) * ldj;
+  const int jn0 = own0 ? N : 0, jn1 = own1 ? N : 0;   // entries of M in each row
   double A0[32], A1[32];
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) {
-    const int c = 32 * w + jj;
+    const int c = 4 * jj + w;
     // unconditional loads (every address lies in this work-group's LDS), masked afterwards
-    const double v0 = row0[jj], v1 = row1[jj];
-    const double f0 = (jj < jn0) ? v0 : 0.0, f1 = (jj < jn1) ? v1 : 0.0;
+    const double v0 = row0[c], v1 = row1[c];
+    const double f0 = (c < jn0) ? v0 : 0.0, f1 = (c < jn1) ? v1 : 0.0;
     A0[jj] = ((!own0) & (c == r0)) ? 1.0 : (((c == r0) & own0) ? d : 0.0) - f0;
     A1[jj] = ((!own1) & (c == r1)) ? 1.0 : (((c == r1) & own1) ? d : 0.0) - f1;
   }
   if (w == 0 && lane == 0) L.pslot[2] = 0u;
   int ord0 = -1, ord1 = -1;
+  int p = 0;
+  double l0 = 0.0, l1 = 0.0;
+  if (w == 0) t4c_search<0>(A0, A1, L, ord0, ord1, p, l0, l1);
   wsync();
-  t4c_col<0>(A0, A1, L, ord0, ord1);
+  t4c_col<0>(A0, A1, L, ord0, ord1, p, l0, l1);
   wsync();
   const int rc = (int)L.pslot[2];
   if (rc) return rc;
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) {
-    const int c = 32 * w + jj;
+    const int c = 4 * jj + w;
     if (own0 && c < N) F[ord0 * ldj + c] = A0[jj];
     if (own1 && c < N) F[ord1 * ldj + c] = A1[jj];
   }
