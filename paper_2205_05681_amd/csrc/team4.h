@@ -61,7 +61,7 @@ struct Team4Lds {
   double* lcol;   // [128]     the LU's multipliers, odd columns (follows prow)
   double* rdg;    // [128]     1 / U_kk
   double* ust;    // [4][s][128] stage vectors, one copy per wavefront (s: the method's stages)
-  unsigned* pslot;  // [16]    the LU's pivot row, by column parity; its first failure code
+  unsigned* pslot;  // [16]    the LU's pivot row, by column parity; [4..7] each wavefront's first failure
   int* perm;        // [128]   the row pivoted at each step
   int* misc;        // [8]     work-queue position broadcast
   static __host__ __device__ size_t doubles(int N, int s) {
@@ -477,11 +477,13 @@ __device__ __forceinline__ void t4c_update(double (&A0)[32], double (&A1)[32], d
 // Column KC's pivot and multipliers, by the wavefront holding the column
 // (local index KC / 4): the exact largest |a| over the unused rows, ties to
 // the lowest row (its first half, then its second); the multipliers replace
-// the column, and the pivot row, the multipliers, 1 / pivot and the first
-// failure code go to LDS (buffer KC & 1).
+// the column, and the pivot row, the multipliers and 1 / pivot go to LDS
+// (buffer KC & 1).  fk keeps the wavefront's first failure, 4 KC + code (its
+// columns come in increasing order), T4_NOFAIL while there is none.
+constexpr unsigned T4_NOFAIL = 4u * T4_NMAX;
 template <int KC>
 __device__ __forceinline__ void t4c_search(double (&A0)[32], double (&A1)[32], Team4Lds& L, int ord0, int ord1,
-                                           int& p, double& l0, double& l1) {
+                                           int& p, double& l0, double& l1, unsigned& fk) {
   constexpr int KK = KC / 4;
   const int lane = t4_lane();
   double* lc = L.prow + 128 * (KC & 1);   // L.prow and L.lcol: two buffers of 128
@@ -518,8 +520,8 @@ __device__ __forceinline__ void t4c_search(double (&A0)[32], double (&A1)[32], T
     L.pslot[KC & 1] = (unsigned)p;
     L.perm[KC] = p;
     L.rdg[KC] = rp;
-    if (L.pslot[2] == 0u && code) L.pslot[2] = (unsigned)code;   // the first failure in column order
   }
+  fk = (fk == T4_NOFAIL && code) ? 4u * KC + (unsigned)code : fk;
   // keep the column's values here (not sunk past the later columns)
   asm volatile("" : "+v"(l0), "+v"(l1));
 }
@@ -530,7 +532,7 @@ __device__ __forceinline__ void t4c_search(double (&A0)[32], double (&A1)[32], T
 // columns from KC / 4 on when w > KC % 4, from KC / 4 + 1 otherwise.
 template <int KC>
 __device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team4Lds& L, int& ord0, int& ord1,
-                                        int p, double l0, double l1) {
+                                        int p, double l0, double l1, unsigned& fk) {
   if constexpr (KC < T4_NMAX) {
     constexpr int W = KC % 4, KK = KC / 4;
     constexpr int W1 = (KC + 1) % 4, K1 = (KC + 1) / 4;   // the next column's wavefront and local index
@@ -551,7 +553,7 @@ __device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team
     if constexpr (KC + 1 < T4_NMAX) {
       if (w == W1) {
         t4c_update<K1, K1 + 1>(A0, A1, l0, l1, pl, ph);
-        t4c_search<KC + 1>(A0, A1, L, ord0, ord1, pn, m0, m1);
+        t4c_search<KC + 1>(A0, A1, L, ord0, ord1, pn, m0, m1, fk);
         t4c_update<K1 + 1>(A0, A1, l0, l1, pl, ph);
       } else if (w > W) {
         t4c_update<KK>(A0, A1, l0, l1, pl, ph);
@@ -560,7 +562,7 @@ __device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team
       }
       wsync();
     }
-    t4c_col<KC + 1>(A0, A1, L, ord0, ord1, pn, m0, m1);
+    t4c_col<KC + 1>(A0, A1, L, ord0, ord1, pn, m0, m1, fk);
   }
 }
 
@@ -590,15 +592,18 @@ __device__ __forceinline__ int t4_lu(double* __restrict__ F, int ldj, int N, dou
     A0[jj] = ((!own0) & (c == r0)) ? 1.0 : (((c == r0) & own0) ? d : 0.0) - f0;
     A1[jj] = ((!own1) & (c == r1)) ? 1.0 : (((c == r1) & own1) ? d : 0.0) - f1;
   }
-  if (w == 0 && lane == 0) L.pslot[2] = 0u;
   int ord0 = -1, ord1 = -1;
   int p = 0;
   double l0 = 0.0, l1 = 0.0;
-  if (w == 0) t4c_search<0>(A0, A1, L, ord0, ord1, p, l0, l1);
+  unsigned fk = T4_NOFAIL;
+  if (w == 0) t4c_search<0>(A0, A1, L, ord0, ord1, p, l0, l1, fk);
   wsync();
-  t4c_col<0>(A0, A1, L, ord0, ord1, p, l0, l1);
+  t4c_col<0>(A0, A1, L, ord0, ord1, p, l0, l1, fk);
+  // the first failure in column order over the four wavefronts
+  if (lane == 0) L.pslot[4 + w] = fk;
   wsync();
-  const int rc = (int)L.pslot[2];
+  const unsigned f = min(min(L.pslot[4], L.pslot[5]), min(L.pslot[6], L.pslot[7]));
+  const int rc = f == T4_NOFAIL ? 0 : (int)(f & 3u);
   if (rc) return rc;
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) {
