@@ -382,3 +382,18 @@ def test_tangent_matches_central_differences(ch4):
         Tp, _ = o.replay(T[c] + 1e-3, P[c], Y[:, c], hs)
         Tm, _ = o.replay(T[c] - 1e-3, P[c], Y[:, c], hs)
         assert dT0 == pytest.approx((Tp - Tm) / 2e-3, rel=1e-6)
+
+
+@pytest.mark.parametrize("name,min_steps", [("large", 40), ("n127", 40)])
+def test_large_mechanisms_react(mech_dir, name, min_steps):
+    """The large synthetic mechanisms (111 and 127 species) are not inert at
+    the mixing-layer states the GPU tests and the benchmark use: with dt =
+    1e-5 s the hottest cells take many controller steps, so the N = 112 and
+    N = 128 paths are compared over long step sequences, not one step."""
+    path, m = synth.mechanism_file(name, mech_dir)
+    o = oracle.Oracle(path)
+    T, P, Y = synth.states_mixing(m, 4096, 210)
+    idx = np.argsort(-T)[:8]
+    r = o.integrate(T[idx], P[idx], np.ascontiguousarray(Y[:, idx]), 1e-5)
+    assert np.all(r["status"] == 0)
+    assert r["n_acc"].max() >= min_steps
