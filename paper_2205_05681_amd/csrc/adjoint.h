@@ -87,6 +87,80 @@ __device__ __forceinline__ double der(double) { return 0.0; }
 __device__ __forceinline__ double der(Dd c) { return c.d; }
 __device__ __forceinline__ Dd gather(Dd v, int src) { return Dd{gather(v.v, src), gather(v.d, src)}; }
 
+// One reaction of the vector-Jacobian product's loop, slots up to SIDE per
+// side (SIDE < MAX_SIDE when every reaction of the wavefront's pass has at
+// most SIDE species a side): qbar, the ln A gradient, and the scatter of
+// wdot and of Cbar through the rates; tacc and bacc collect the lane's sums
+// of qbar dq/dT and qbar beta.
+template <class S, int SIDE>
+__device__ __forceinline__ void vjp_reaction(const MechView& M, const RxnRec& R, int j, S T, S lnT, S iT, S ctot,
+                                             TeamLdsT<S>& L, S* dummy, double* __restrict__ pbar, bool add_value,
+                                             S& tacc, S& bacc) {
+  const RateOutT<S> r = reaction_rate<S, SIDE>(M, R, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
+                                               LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, true);
+  const int nr = R.nr, np = R.np;
+  int ks[6], nus[6];
+  bool on[6];
+  S cs[6], ws[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    on[q] = (q % 3 < SIDE) && ((q < 3) ? (q < nr) : (q - 3 < np));
+    ks[q] = R.sp[q];            // unused slots hold species 0 and coefficient 0
+    nus[q] = R.nu[q];
+    cs[q] = (q % 3 < SIDE) ? L.conc[ks[q]] : sc<S>(0.0);
+    ws[q] = (q % 3 < SIDE) ? L.tb[ks[q]] : sc<S>(0.0);
+  }
+  // qbar: reactants, then products, in slot order
+  S qb = sc<S>(0.0);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q % 3 >= SIDE) continue;
+    const double v = (q < 3) ? -(double)nus[q] : (double)nus[q];
+    if (on[q]) qb += v * ws[q];
+  }
+  const S c = r.q * qb;
+  pbar[j] += (add_value ? val(c) : 0.0) + der(c);
+  // d q / d C of slot q, as in team_rhs_jac
+  S dq[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int s0 = q < 3 ? 0 : 3;
+    S d = (q < 3) ? r.kf : r.kr;
+#pragma unroll
+    for (int l = 0; l < SIDE; ++l) {
+      const int v = (s0 + l == q) ? nus[s0 + l] - 1 : nus[s0 + l];
+      const S cc = cs[s0 + l];
+      d = (v >= 1) ? d * cc : d;
+      d = (v >= 2) ? d * cc : d;
+      d = (v >= 3) ? d * cc : d;
+    }
+    dq[q] = d * (double)(q < 3 ? nus[q] : -nus[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    if (q % 3 >= SIDE) continue;
+    const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
+    lds_add(on[q] ? &L.wdot[ks[q]] : dummy, vk * r.q);
+    lds_add(on[q] ? &L.gb[ks[q]] : dummy, qb * dq[q]);
+  }
+  tacc += qb * (r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT);
+  if (R.type != RX_ELEM) {
+    // [M] = sum C + sum (alpha - 1) C: the uniform part summed per lane, the
+    // listed efficiencies scattered (the first four read together)
+    const S qbb = qb * r.beta;
+    bacc += qbb;
+    const int e0 = R.e0, e1 = R.e1;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = (e0 + t < e1) ? e0 + t : e0;
+      const int m = M.eff_idx[e];
+      const double am1 = M.eff_am1[e];
+      lds_add((e0 + t < e1) ? &L.gb[m] : dummy, qbb * am1);
+    }
+    for (int e = e0 + 4; e < e1; ++e) lds_add(&L.gb[M.eff_idx[e]], qbb * M.eff_am1[e]);
+  }
+}
+
 // J(y)^T mu and f_p(y)^T mu (added to pbar) without forming J: reverse mode
 // through f.  With G = mu^T f,
 //   f_T = Tdot = -num/D,  num = sum_k h_k wdot_k,  D = sum_k C_k cp_k,
@@ -136,67 +210,12 @@ __device__ S team_vjp(const MechView& M, double P, S y, double mu, TeamLdsT<S>& 
   for (int j = lane; j < Nr; j += 64) {
     const RxnRec R = nx;
     nx = load_rxn(M, j + 64 < Nr ? j + 64 : j, lnA);
-    const RateOutT<S> r = reaction_rate(M, R, T, lnT, iT, ctot, LaneT<S>{L.conc, 1},
-                                        LaneT<S>{L.gib, 1}, LaneT<S>{L.hrt, 1}, true);
-    const int nr = R.nr, np = R.np;
-    int ks[6], nus[6];
-    bool on[6];
-    S cs[6], ws[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      on[q] = (q < 3) ? (q < nr) : (q - 3 < np);
-      ks[q] = R.sp[q];            // unused slots hold species 0 and coefficient 0
-      nus[q] = R.nu[q];
-      cs[q] = L.conc[ks[q]];
-      ws[q] = L.tb[ks[q]];
-    }
-    // qbar: reactants, then products, in slot order
-    S qb = sc<S>(0.0);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const double v = (q < 3) ? -(double)nus[q] : (double)nus[q];
-      if (on[q]) qb += v * ws[q];
-    }
-    const S c = r.q * qb;
-    pbar[j] += (add_value ? val(c) : 0.0) + der(c);
-    // d q / d C of slot q, as in team_rhs_jac
-    S dq[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int s0 = q < 3 ? 0 : 3;
-      S d = (q < 3) ? r.kf : r.kr;
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        const int v = (s0 + l == q) ? nus[s0 + l] - 1 : nus[s0 + l];
-        const S cc = cs[s0 + l];
-        d = (v >= 1) ? d * cc : d;
-        d = (v >= 2) ? d * cc : d;
-        d = (v >= 3) ? d * cc : d;
-      }
-      dq[q] = d * (double)(q < 3 ? nus[q] : -nus[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const double vk = (q < 3) ? -(double)nus[q] : (double)nus[q];
-      lds_add(on[q] ? &L.wdot[ks[q]] : dummy, vk * r.q);
-      lds_add(on[q] ? &L.gb[ks[q]] : dummy, qb * dq[q]);
-    }
-    tacc += qb * (r.dlnk_dT * r.q + r.kr_rr * r.dlnKc_dT);
-    if (R.type != RX_ELEM) {
-      // [M] = sum C + sum (alpha - 1) C: the uniform part summed per lane, the
-      // listed efficiencies scattered (the first four read together)
-      const S qbb = qb * r.beta;
-      bacc += qbb;
-      const int e0 = R.e0, e1 = R.e1;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int e = (e0 + t < e1) ? e0 + t : e0;
-        const int m = M.eff_idx[e];
-        const double am1 = M.eff_am1[e];
-        lds_add((e0 + t < e1) ? &L.gb[m] : dummy, qbb * am1);
-      }
-      for (int e = e0 + 4; e < e1; ++e) lds_add(&L.gb[M.eff_idx[e]], qbb * M.eff_am1[e]);
-    }
+    // most passes hold two-by-two reactions only: then the third slot of each
+    // side is left out (a wave-uniform choice, once per pass)
+    if (__all(R.nr <= 2 && R.np <= 2))
+      vjp_reaction<S, 2>(M, R, j, T, lnT, iT, ctot, L, dummy, pbar, add_value, tacc, bacc);
+    else
+      vjp_reaction<S, MAX_SIDE>(M, R, j, T, lnT, iT, ctot, L, dummy, pbar, add_value, tacc, bacc);
   }
   wsync();
   S num = sc<S>(0.0), cpw = sc<S>(0.0), W = sc<S>(0.0), muw = sc<S>(0.0);
