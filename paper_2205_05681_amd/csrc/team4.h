@@ -635,9 +635,11 @@ __device__ __forceinline__ V2 t4_solve(const double* __restrict__ F, int ldj, in
   V2 b;
   b.a = own0 ? g0 : 0.0;
   b.b = own1 ? g1 : 0.0;
-  // forward: L y = P b
+  // forward: L y = P b (blocks of eight columns; those past N change nothing
+  // and are skipped, a wave-uniform test)
 #pragma unroll
   for (int k0 = 0; k0 < T4_NMAX; k0 += 8) {
+    if (k0 >= N) break;
     double la[8], lb[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -663,6 +665,7 @@ __device__ __forceinline__ V2 t4_solve(const double* __restrict__ F, int ldj, in
   const V2 rd{rd0, rd1};
 #pragma unroll
   for (int k1 = T4_NMAX - 1; k1 >= 0; k1 -= 8) {
+    if (k1 - 7 >= N) continue;   // every column of the block past N
     double ua[8], ub[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
