@@ -532,8 +532,12 @@ __device__ __forceinline__ void t4c_search(double (&A0)[32], double (&A1)[32], T
 // columns from KC / 4 on when w > KC % 4, from KC / 4 + 1 otherwise.
 template <int KC>
 __device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team4Lds& L, int& ord0, int& ord1,
-                                        int p, double l0, double l1, unsigned& fk) {
+                                        int p, double l0, double l1, unsigned& fk, int N) {
   if constexpr (KC < T4_NMAX) {
+    // the padding columns past N change no real row (their entries there are
+    // zero): every wavefront stops at the same step (N is uniform)
+    if constexpr (KC > 64)
+      if (KC >= N) return;
     constexpr int W = KC % 4, KK = KC / 4;
     constexpr int W1 = (KC + 1) % 4, K1 = (KC + 1) / 4;   // the next column's wavefront and local index
     const int w = t4_wave(), lane = t4_lane();
@@ -562,7 +566,7 @@ __device__ __forceinline__ void t4c_col(double (&A0)[32], double (&A1)[32], Team
       }
       wsync();
     }
-    t4c_col<KC + 1>(A0, A1, L, ord0, ord1, pn, m0, m1, fk);
+    t4c_col<KC + 1>(A0, A1, L, ord0, ord1, pn, m0, m1, fk, N);
   }
 }
 
@@ -598,7 +602,7 @@ __device__ __forceinline__ int t4_lu(double* __restrict__ F, int ldj, int N, dou
   unsigned fk = T4_NOFAIL;
   if (w == 0) t4c_search<0>(A0, A1, L, ord0, ord1, p, l0, l1, fk);
   wsync();
-  t4c_col<0>(A0, A1, L, ord0, ord1, p, l0, l1, fk);
+  t4c_col<0>(A0, A1, L, ord0, ord1, p, l0, l1, fk, N);
   // the first failure in column order over the four wavefronts
   if (lane == 0) L.pslot[4 + w] = fk;
   wsync();
